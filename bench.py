@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Throughput of the batched DALM solver on one MI355X.
+
+One step = one pass of the solver over one batch of synthetic instances
+already resident in HBM: the per-instance penalties and constant term, the
+iterations (z-, y-, w-steps fused in one MFMA GEMM launch per iteration, the
+convergence test and active-set compaction), the output extraction and the
+FP64 optimality certificate of every instance.  The dictionary's one-time
+FP64 factorisation (the plan) is built before the timed region and reported
+separately as ``plan_ms``.
+
+Prints ONE JSON line on stdout; everything else goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks (dense): HBM3E 8 TB/s; MFMA BF16 2.5 PFLOP/s, FP32 157.3 TFLOP/s
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "split": 2500.0}
+
+WORKLOADS = {
+    # B 1200 x 700 (100 classes x 7), A = [B, I]; 512 test vectors, 30 % corrupted
+    "cab-1200x700-n512": dict(m=1200, classes=100, per_class=7, N=512, frac=0.3, cfg=3),
+    # B 4800 x 2100 (300 classes x 7); 2048 test vectors, corruption U[0, 0.5] each
+    "cab-4800x2100-n2048": dict(m=4800, classes=300, per_class=7, N=2048, frac="uneven", cfg=4),
+}
+DEFAULT_WORKLOAD = "cab-1200x700-n512"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="bf16_refine", choices=["fp32", "bf16_refine", "bf16x3"])
+    ap.add_argument("--tol", type=float, default=4e-6)
+    ap.add_argument("--max-iter", type=int, default=40000)
+    ap.add_argument("--check-instances", type=int, default=4,
+                    help="instances whose x is compared with the exact LP optimum")
+    ap.add_argument("--plain-instances", type=int, default=8,
+                    help="instances solved one per launch with FP32 for the plain-path figure")
+    ap.add_argument("--cpu-instances", type=int, default=2,
+                    help="instances the FP64 CPU oracle solves for the cpu_baseline figure")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration under rocprofv3)")
+    return ap.parse_args()
+
+
+def traffic_record(src_hash):
+    """HBM bytes per launch of the iteration kernel from the committed PMC
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "dalm_iteration_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != src_hash:
+        return None
+    return rec
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("iter.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1007_3753_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); instances are "
+              "independent, so N GPUs would each run this same per-GPU workload.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1007_3753_amd import Plan
+    from workloads import cab_problem
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.time()
+    P = cab_problem(m=wl["m"], classes=wl["classes"], per_class=wl["per_class"], N=wl["N"],
+                    frac=wl["frac"], cfg=wl["cfg"])
+    log(f"workload {args.workload}: B {P.A.shape}, N {P.N}, generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    A = torch.as_tensor(P.A, device=dev)
+    b = torch.as_tensor(P.b, device=dev)
+    m, nd, N = P.m, P.n_dict, P.N
+    n_full = nd + m
+    plan = Plan(A, structure="cab", precision=args.precision, max_batch=N, time_kernels=True)
+    plan_ms = plan.last_stats()["plan_ms"]
+    log(f"plan ({args.precision}) built in {plan_ms:.1f} ms")
+
+    def step():
+        r = plan.solve(b, tol=args.tol, max_iter=args.max_iter)
+        rep = plan.kkt(b, r.x, e=r.e, y=r.y)
+        return r, rep
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    agg = dict(timed_ms=0.0, timed_launches=0.0, launch_fp32=0.0, launch_bf16=0.0, launch_split=0.0,
+               cols_fp32=0.0, cols_bf16=0.0, cols_split=0.0)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        r, rep = step()
+        st = plan.last_stats()
+        for k in agg:
+            agg[k] += st[k]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N / (ms_per_step / 1e3)
+    iters = r.iters.cpu().numpy()
+    status = r.status.cpu().numpy()
+    rep = rep.cpu().numpy()
+    log(f"{args.steps} steps: {ms_per_step:.2f} ms/step -> {value:.1f} solves/s; iterations "
+        f"mean {iters.mean():.0f} max {iters.max()}; status counts {np.bincount(status, minlength=3).tolist()}")
+
+    # ---- roofline of the iteration kernel (gemm_kernel<EPI_DALM>) -----------
+    n_pad = (n_full + 63) // 64 * 64
+    cols = {"fp32": agg["cols_fp32"], "bf16": agg["cols_bf16"], "split": agg["cols_split"]}
+    launches = {"fp32": agg["launch_fp32"], "bf16": agg["launch_bf16"], "split": agg["launch_split"]}
+    flops = {k: 2.0 * n_full * n_full * c for k, c in cols.items()}
+    op_bytes = {"fp32": 4, "bf16": 2, "split": 4}
+    # operator read once per launch per arithmetic present + per instance: u read,
+    # (v, w, c) read, (v, w, u) written, FP32
+    bytes_total = sum(n_full * n_full * op_bytes[k] * launches[k] for k in launches) + \
+        28.0 * n_full * sum(cols.values())
+    kern_s = agg["timed_ms"] / 1e3
+    nl = max(agg["timed_launches"], 1.0)
+    t_mfma = sum(flops[k] / (PEAK_TFLOPS[k] * 1e12) for k in flops)
+    t_hbm = bytes_total / (PEAK_HBM_GBS * 1e9)
+    tot_flops = sum(flops.values())
+    trec = traffic_record(kernel_source_hash())
+    traffic = None if trec is None else trec.get("hbm_bytes_per_launch_at_workload", {}).get(args.workload)
+    if t_mfma >= t_hbm:
+        eff_peak = tot_flops / t_mfma / 1e12 if t_mfma > 0 else 0.0
+        achieved = tot_flops / kern_s / 1e12 if kern_s > 0 else 0.0
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(eff_peak, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / eff_peak, 4) if eff_peak else None,
+                "traffic": traffic}
+    else:
+        achieved = bytes_total / kern_s / 1e9 if kern_s > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+    roof.update({
+        "kernel": "gemm_kernel<EPI_DALM>",
+        "avg_launch_us": round(1e6 * kern_s / nl, 3),
+        "launches_timed": int(agg["timed_launches"]),
+        "algorithmic_flops_per_launch": round(tot_flops / nl),
+        "algorithmic_bytes_per_launch": round(bytes_total / nl),
+        "mfma_frac_of_bf16_peak": round(tot_flops / kern_s / 2.5e15, 4) if kern_s > 0 else None,
+        "kernel_share_of_step": round(agg["timed_ms"] / (ms_per_step * args.steps), 3),
+    })
+    log(f"iteration kernel: {nl:.0f} launches, avg {1e6 * kern_s / nl:.2f} us; "
+        f"{tot_flops / kern_s / 1e12:.1f} algorithmic TFLOP/s, {bytes_total / kern_s / 1e9:.0f} GB/s")
+
+    out = {
+        "metric": "solves/sec at rel. err <=1e-4 vs FP64 oracle (batched DALM, cross-and-bouquet)",
+        "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16_refine": "bf16+split-bf16 (f32 accumulate)",
+                  "bf16x3": "split-bf16 (f32 accumulate)"}[args.precision],
+        "data": "synthetic (seeded cross-and-bouquet stand-in for face images; no dataset)",
+        "config": {"workload": args.workload, "m": m, "n_dict": nd, "n_full": n_full, "N": N,
+                   "problem": "P1", "structure": "cab", "method": "dalm",
+                   "precision": args.precision, "tol": args.tol, "max_iter": args.max_iter},
+        "plan_ms": round(plan_ms, 2),
+        "iterations": {"mean": float(iters.mean()), "max": int(iters.max())},
+        "status_counts": np.bincount(status, minlength=3).tolist(),
+        "kkt_max": {"primal": float(rep[:, 0].max()), "dual_inf": float(rep[:, 1].max()),
+                    "gap": float(rep[:, 3].max())},
+        "roofline": roof,
+    }
+
+    # ---- accuracy against the exact optimum (HiGHS LP on [B, I]) ------------
+    if not args.no_check and args.check_instances > 0:
+        from oracle import p1_lp, full_matrix
+        Af = full_matrix(P.A, "cab")
+        idx = np.unique(np.linspace(0, N - 1, args.check_instances).astype(int))
+        X = r.x.cpu().numpy().astype(np.float64)
+        errs = []
+        for j in idx:
+            w_lp, _ = p1_lp(Af, P.b[:, j])
+            errs.append(float(np.linalg.norm(X[:, j] - w_lp[:nd]) / np.linalg.norm(w_lp[:nd])))
+        out["rel_err_vs_lp"] = {"instances": idx.tolist(), "max": max(errs), "all": errs}
+        log(f"rel. err of x vs LP optimum on {len(idx)} instances: max {max(errs):.2e}")
+
+    # ---- plain path: one instance per launch, FP32 ----------------------------
+    if not args.no_plain and args.plain_instances > 0:
+        plain = Plan(A, structure="cab", precision="fp32", max_batch=1)
+        k = min(args.plain_instances, N)
+        plain.solve(b[:, :1], tol=args.tol, max_iter=args.max_iter)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for j in range(k):
+            plain.solve(b[:, j:j + 1], tol=args.tol, max_iter=args.max_iter)
+        torch.cuda.synchronize()
+        ps = k / (time.perf_counter() - t)
+        out["plain"] = {"solves_per_s": round(ps, 3), "instances": k, "precision": "fp32",
+                        "batched_over_plain": round(value / ps, 1)}
+        log(f"plain one-instance-per-launch FP32: {ps:.2f} solves/s -> batched is {value / ps:.0f}x")
+        plain.close()
+
+    # ---- CPU baseline: the FP64 oracle on this host's cores ------------------
+    if not args.no_cpu_baseline and args.cpu_instances > 0:
+        from oracle import dalm as oracle_dalm
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count()
+        k = min(args.cpu_instances, N)
+        t = time.perf_counter()
+        o = oracle_dalm(P.A, P.b[:, :k], structure="cab", tol=args.tol, max_iter=args.max_iter)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {
+            "value": round(k / dt, 5), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {k} of the {N} instances, FP64 NumPy/SciPy Algorithm 2 with a "
+                      f"Cholesky y-step, same tol ({args.tol:g}); {dt:.1f} s, iterations "
+                      f"{o.iters.tolist()}"}
+        log(f"CPU oracle: {k} instances in {dt:.1f} s on {threads} threads")
+
+    if args.copy_calibration:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = x.numel() * 4
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

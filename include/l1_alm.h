@@ -1,0 +1,184 @@
+/*
+ * l1_alm.h -- C ABI of libl1alm, batched augmented-Lagrangian l1 solvers for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problems (Sec. I of Yang, Zhou, Ganesh, Sastry, Ma, "Fast l1-minimization
+ * algorithms for robust face recognition"):
+ *   (P1)        min ||x||_1                      s.t. b = A x            eq. (l1)
+ *   (P_{1,2})   min ||x||_1                      s.t. ||b - A x||_2 <= eps  eq. (l1-l2)
+ *   (QP_lambda) min 1/2 ||b - A x||_2^2 + lambda ||x||_1                eq. (Lagrangian)
+ * and the cross-and-bouquet (CAB) form of (P1) (Sec. II-A, eq. (CAB)):
+ *               min ||w||_1  s.t. b = [B, I] w,  w = [x; e].
+ * Methods: the dual ALM (DALM, Sec. V-B, Algorithm 2) and the primal ALM
+ * (PALM, Sec. V-A, eq. (alm) and Algorithm 1, FISTA inner solver).
+ *
+ * Conventions for every entry point
+ *   - Matrices are column-major FP32 with an explicit leading dimension.  A
+ *     batch of N right-hand sides is an m x N matrix: one column per instance.
+ *   - Every array argument is a DEVICE pointer on the current HIP device,
+ *     owned by the caller; the library never keeps a caller pointer past the
+ *     call that received it.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls enqueue work on it; outputs are valid after the stream is
+ *     synchronised.  l1_alm_solve synchronises `stream` itself a few times per
+ *     solve to read the number of still-active instances.
+ *   - Return value: 0 on success or a negative L1_E* code; the message of the
+ *     last failure on the calling thread is returned by l1_alm_last_error().
+ *   - Per-instance outcomes are not errors: they are reported in `status`.
+ *   - One solve at a time per plan; a plan may move between host threads
+ *     only with external locking.
+ */
+#ifndef L1_ALM_H_
+#define L1_ALM_H_
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define L1_OK          0
+#define L1_EINVAL     -1   /* bad size, leading dimension, NULL pointer or option   */
+#define L1_ENOTSPD    -2   /* FP64 Cholesky met a pivot <= 0 (dependent rows of A)   */
+#define L1_ENOMEM     -3   /* device allocation failed                              */
+#define L1_EHIP       -4   /* HIP runtime error; message in l1_alm_last_error()     */
+#define L1_ENODEVICE  -5   /* no gfx950 device visible                              */
+#define L1_ENOTAPE    -6   /* l1_alm_backward without a recorded fixed-count solve   */
+
+/* per-instance status */
+#define L1_CONVERGED   0
+#define L1_MAXITER     1
+#define L1_NONFINITE   2
+
+typedef enum { L1_P1 = 0, L1_P12 = 1, L1_QPLAMBDA = 2 } l1_problem;
+typedef enum { L1_DENSE = 0, L1_CAB = 1 } l1_structure;
+typedef enum { L1_DALM = 0, L1_PALM = 1 } l1_method;
+/* Arithmetic of the per-iteration matrix products.  State, elementwise
+ * updates and accumulation are FP32 in every mode; the operator is rounded
+ * from FP64 once per plan.
+ *   L1_FP32        FP32 MFMA products.
+ *   L1_BF16_REFINE BF16 MFMA products until an instance's relative change and
+ *                  gap are both <= refine_switch (where BF16 rounding stalls
+ *                  them), then split-BF16 products (B = B_hi + B_lo,
+ *                  u = u_hi + u_lo; hi*hi + hi*lo + lo*hi with FP32
+ *                  accumulation, ~16 significant bits) until convergence.
+ *                  An instance can only be declared converged in the split
+ *                  phase.
+ *   L1_BF16X3      split-BF16 products for every iteration.                 */
+typedef enum { L1_FP32 = 0, L1_BF16_REFINE = 1, L1_BF16X3 = 2 } l1_precision;
+
+typedef struct l1_alm_plan_s* l1_alm_plan_t;   /* opaque, owned by the library */
+
+typedef struct {
+  int m;                 /* rows of the dictionary (length of b)                     */
+  int n_dict;            /* columns of the dictionary (B for CAB, A otherwise)       */
+  int lda;               /* leading dimension of the dictionary passed to the plan   */
+  int problem;           /* l1_problem                                               */
+  int structure;         /* l1_structure; L1_CAB: the caller passes B, A = [B, I]    */
+  int method;            /* l1_method                                                */
+  int precision;         /* l1_precision                                             */
+  int max_batch;         /* upper bound on N for every solve with this plan (>= 1)   */
+  double lambda;         /* QP_lambda weight (> 0); ignored otherwise                */
+  double beta;           /* DALM penalty.  <= 0: per instance ||b||_1 / m.  Required
+                            (> 0) for DALM on QP_lambda, where it enters the factor. */
+  double xi;             /* PALM penalty.  <= 0: per instance 2 m / ||b||_1 (Sec. V-A) */
+  double xi_growth;      /* PALM: xi <- xi * xi_growth after each outer step (<= 0 -> 1) */
+  int max_inner;         /* PALM: cap on FISTA steps per outer step (<= 0 -> 100)     */
+  double tol_inner;      /* PALM: FISTA relative-change tolerance (<= 0 -> solve tol) */
+  double refine_switch;  /* L1_BF16_REFINE: switch threshold (<= 0 -> 3e-3)           */
+  int record_tape;       /* 1: fixed-count DALM solves keep checkpoints for backward */
+  int checkpoint_every;  /* checkpoint spacing in iterations (<= 0 -> 10)            */
+  int time_kernels;      /* 1: time every per-iteration product launch with HIP
+                            events on the solve stream (see l1_alm_last_stats)      */
+} l1_alm_desc;
+
+/* Build a plan for the dictionary A_dev (m x n_dict, column-major, leading
+ * dimension desc->lda >= m).
+ *   DALM: forms, on the GPU in FP64, the Gram matrix of the full matrix
+ *   (A A^T, B B^T + I for CAB, A A^T + I for the P_{1,2} splitting, plus
+ *   (lambda/beta) I for QP_lambda), its Cholesky factor (Sec. V-B: the
+ *   y-step "directly uses" the inverse) and from it the operators the
+ *   iteration applies; FP64 is used only here and in l1_alm_kkt.
+ *   PALM: forms A^T A in FP64 and L = ||A^T A||_2 by FP64 power iteration
+ *   (the Lipschitz constant of Sec. IV-A used in Algorithm 1).
+ * Returns L1_ENOTSPD when the Gram matrix is not positive definite, L1_EINVAL
+ * for an unsupported combination (QP_lambda or P_{1,2} with L1_CAB).
+ * The plan copies A; the caller may free A_dev after the call returns.   */
+int l1_alm_plan(const l1_alm_desc* desc, const float* A_dev, void* stream,
+                l1_alm_plan_t* out);
+
+/* Solve N instances (columns of b_dev, m x N, leading dimension ldb >= m).
+ *   eps_dev   P_{1,2}: N radii (device); NULL otherwise.
+ *   tol       stopping tolerance: an instance stops after iteration k when
+ *             ||w_k - w_{k-1}|| <= tol ||w_k|| and the complementarity gap of
+ *             the l1 block | ||w||_1 - w^T A^T y | <= tol ||w||_1 (DALM), or
+ *             when the relative change and the relative primal residual
+ *             ||b - A x - e|| / ||b|| are both <= tol (PALM outer loop).
+ *             For DALM the test uses max(tol, floor) with the floor of the
+ *             products' arithmetic (FP32 2e-6, split BF16 4e-6).
+ *   max_iter  > 0: iteration cap (DALM iterations / PALM outer steps);
+ *             < 0: run exactly -max_iter iterations with no stopping test
+ *             (the unrolled map used by l1_alm_backward; DALM only).
+ *   w0_dev, y0_dev  DALM warm start (n_full x N with ld n_full, m x N with
+ *             ld m), or NULL for w0 = 0, y0 = 0 (Algorithm 2 input).
+ *   x_dev     n_dict x N output, leading dimension ldx >= n_dict.
+ *   e_dev     m x N output (ld lde >= m): the e-block of w for CAB, the
+ *             split residual block for P_{1,2} (and QP_lambda under PALM);
+ *             may be NULL.
+ *   y_dev     m x N dual output (DALM; ld ldy >= m) or NULL.
+ *   iters_dev, status_dev  N ints each (may be NULL).
+ * n_full = n_dict + m for CAB and P_{1,2}, n_dict otherwise.             */
+int l1_alm_solve(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
+                 const float* eps_dev, float tol, int max_iter,
+                 const float* w0_dev, const float* y0_dev,
+                 float* x_dev, int ldx, float* e_dev, int lde,
+                 float* y_dev, int ldy, int* iters_dev, int* status_dev,
+                 void* stream);
+
+/* Reverse-mode gradient of the last recorded fixed-count CAB DALM solve
+ * (max_iter < 0, desc.record_tape = 1): given adjoints gx (n_dict x N, ld
+ * n_dict) and ge (m x N, ld m) of its outputs x and e, writes
+ * gb (m x N, ld m, overwritten) = d<gx,x> + <ge,e> / d b and ADDS the
+ * gradient with respect to the dictionary into gA (m x n_dict, ld m).
+ * The iterations are recomputed segment by segment from checkpoints kept
+ * every desc.checkpoint_every iterations.  beta is held constant.
+ * Returns L1_ENOTAPE if no tape was recorded.                            */
+int l1_alm_backward(l1_alm_plan_t plan, const float* gx_dev, const float* ge_dev,
+                    float* gb_dev, float* gA_dev, void* stream);
+
+/* FP64 optimality report for N solutions (the LP duality pair of Sec. III-A
+ * and V-B; for QP_lambda the optimality condition of Sec. III-B).  Writes
+ * report_dev[4*j + {0,1,2,3}] = {relative primal residual, dual infeasibility
+ * max(||A^T y||_inf - 1, 0), sign disagreement on the support, relative
+ * gap} for instance j.  Arguments as in l1_alm_solve; e_dev / y_dev may be
+ * NULL when the problem has no such block (y is not used for QP_lambda). */
+int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
+               const float* eps_dev, const float* x_dev, int ldx,
+               const float* e_dev, int lde, const float* y_dev, int ldy,
+               double* report_dev, void* stream);
+
+/* Statistics of the last l1_alm_solve on this plan; writes min(n, 14)
+ * doubles to out (host memory):
+ *   [0..2]  launches of the per-iteration product that had work, by the
+ *           arithmetic of their tiles: FP32, BF16, split BF16
+ *   [3..5]  instances summed over those launches, by arithmetic
+ *   [6]     total duration (ms) of the timed product launches that had work
+ *           (desc.time_kernels = 1; HIP events around each launch), else 0
+ *   [7]     number of such timed launches
+ *   [8]     iterations run (the largest per-instance count)
+ *   [9]     wall time of the call on the host (ms)
+ *   [10]    one-time plan construction time (ms, host wall clock)
+ *   [11..13] reserved (0)
+ * The tolerance floors used by the stopping test are FP32 2e-6 and split
+ * BF16 4e-6 (the level where rounding noise stalls the test).             */
+int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n);
+
+/* Release the plan and all device memory it owns. */
+int l1_alm_destroy(l1_alm_plan_t plan);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* l1_alm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* L1_ALM_H_ */

@@ -1,0 +1,147 @@
+"""Thin Python binding over the libl1alm C ABI.
+
+Only argument marshalling happens here: tensors are laid out column-major
+(one instance per column) and their device pointers, sizes and the current
+HIP stream are handed to the library, which runs every step of the method.
+PyTorch provides device memory and streams.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+PROBLEMS = {"p1": 0, "p12": 1, "qp": 2}
+STRUCTURES = {"dense": 0, "cab": 1}
+METHODS = {"dalm": 0, "palm": 1}
+PRECISIONS = {"fp32": 0, "bf16_refine": 1, "bf16x3": 2}
+CONVERGED, MAXITER, NONFINITE = 0, 1, 2
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _colmajor(t, rows):
+    """(rows, N) tensor -> contiguous float32 (N, rows) buffer = column-major (rows x N)."""
+    t = torch.as_tensor(t)
+    if t.dim() == 1:
+        t = t[:, None]
+    if t.shape[0] != rows:
+        raise ValueError(f"expected {rows} rows, got shape {tuple(t.shape)}")
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    return t.t().contiguous().to(torch.float32)
+
+
+class SolveResult:
+    def __init__(self, x, e, y, iters, status):
+        self.x, self.e, self.y, self.iters, self.status = x, e, y, iters, status
+
+    def __iter__(self):
+        return iter((self.x, self.e, self.y, self.iters, self.status))
+
+
+class Plan:
+    """A factorised dictionary ready for batched solves.
+
+    ``A`` is the (m, n_dict) dictionary on the GPU (B for ``structure="cab"``,
+    where the solver works on [B, I]).  See include/l1_alm.h for the options.
+    """
+
+    def __init__(self, A, *, problem="p1", structure="dense", method="dalm",
+                 precision="fp32", max_batch=1, lam=0.0, beta=0.0, xi=0.0, xi_growth=1.0,
+                 max_inner=100, tol_inner=0.0, refine_switch=0.0, record_tape=False,
+                 checkpoint_every=10, time_kernels=False):
+        self.lib = _lib.load()
+        A = torch.as_tensor(A)
+        if A.dim() != 2 or not A.is_cuda:
+            raise ValueError("A must be a 2-D GPU tensor")
+        self.m, self.n_dict = int(A.shape[0]), int(A.shape[1])
+        self.problem, self.structure, self.method = problem, structure, method
+        self.precision = precision
+        self.max_batch = int(max_batch)
+        self.split = structure == "cab" or problem == "p12"
+        self.n_full = self.n_dict + (self.m if self.split else 0)
+        self.device = A.device
+        Ac = A.t().contiguous().to(torch.float32)   # column-major m x n_dict
+        d = _lib.l1_alm_desc()
+        d.m, d.n_dict, d.lda = self.m, self.n_dict, self.m
+        d.problem, d.structure = PROBLEMS[problem], STRUCTURES[structure]
+        d.method, d.precision = METHODS[method], PRECISIONS[precision]
+        d.max_batch = self.max_batch
+        d.lam, d.beta, d.xi, d.xi_growth = float(lam), float(beta), float(xi), float(xi_growth)
+        d.max_inner, d.tol_inner, d.refine_switch = int(max_inner), float(tol_inner), float(refine_switch)
+        d.record_tape, d.checkpoint_every = int(bool(record_tape)), int(checkpoint_every)
+        d.time_kernels = int(bool(time_kernels))
+        self.desc = d
+        h = ctypes.c_void_p()
+        if Ac.numel() == 0:
+            Ac = torch.zeros(1, device=A.device)
+        _lib.check(self.lib.l1_alm_plan(ctypes.byref(d), _ptr(Ac), _stream(), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.l1_alm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, *, tol=1e-6, max_iter=10000, eps=None, w0=None, y0=None,
+              want_y=True):
+        """Solve the columns of ``b`` (m, N).  Returns SolveResult with
+        x (n_dict, N), e (m, N) or None, y (m, N) or None, iters (N,), status (N,).
+        ``max_iter < 0`` runs exactly ``-max_iter`` iterations."""
+        bc = _colmajor(b, self.m)
+        N = bc.shape[0]
+        dev = bc.device
+        x = torch.empty(N, self.n_dict, device=dev, dtype=torch.float32)
+        e = torch.empty(N, self.m, device=dev, dtype=torch.float32) if self.split else None
+        y = torch.empty(N, self.m, device=dev, dtype=torch.float32) if (want_y and self.method == "dalm") else None
+        iters = torch.empty(N, device=dev, dtype=torch.int32)
+        status = torch.empty(N, device=dev, dtype=torch.int32)
+        epsc = None
+        if eps is not None:
+            epsc = torch.as_tensor(eps, dtype=torch.float32, device=dev).reshape(-1).contiguous()
+            if epsc.numel() == 1 and N > 1:
+                epsc = epsc.expand(N).contiguous()
+        w0c = _colmajor(w0, self.n_full) if w0 is not None else None
+        y0c = _colmajor(y0, self.m) if y0 is not None else None
+        _lib.check(self.lib.l1_alm_solve(
+            self.handle, _ptr(bc), self.m, N, _ptr(epsc), ctypes.c_float(tol), int(max_iter),
+            _ptr(w0c), _ptr(y0c), _ptr(x), max(self.n_dict, 1), _ptr(e), self.m, _ptr(y), self.m,
+            _ptr(iters), _ptr(status), _stream()))
+        return SolveResult(x.t(), None if e is None else e.t(), None if y is None else y.t(),
+                           iters, status)
+
+    def kkt(self, b, x, e=None, y=None, eps=None):
+        """FP64 certificate per instance: (N, 4) float64 tensor of
+        [primal residual, dual infeasibility, sign disagreement, gap]."""
+        bc = _colmajor(b, self.m)
+        N = bc.shape[0]
+        xc = _colmajor(x, self.n_dict)
+        ec = _colmajor(e, self.m) if e is not None else None
+        yc = _colmajor(y, self.m) if y is not None else None
+        epsc = None if eps is None else torch.as_tensor(eps, dtype=torch.float32, device=bc.device).reshape(-1).contiguous()
+        rep = torch.empty(N, 4, device=bc.device, dtype=torch.float64)
+        _lib.check(self.lib.l1_alm_kkt(self.handle, _ptr(bc), self.m, N, _ptr(epsc), _ptr(xc),
+                                       max(self.n_dict, 1), _ptr(ec), self.m, _ptr(yc), self.m,
+                                       _ptr(rep), _stream()))
+        return rep
+
+    STAT_KEYS = ("launch_fp32", "launch_bf16", "launch_split", "cols_fp32", "cols_bf16",
+                 "cols_split", "timed_ms", "timed_launches", "iterations", "solve_ms", "plan_ms")
+
+    def last_stats(self):
+        out = (ctypes.c_double * 14)()
+        _lib.check(self.lib.l1_alm_last_stats(self.handle, out, 14))
+        return dict(zip(self.STAT_KEYS, list(out)))

@@ -1,0 +1,384 @@
+// C ABI of libl1alm: plan construction, the solve drivers, the FP64
+// certificate and error reporting.  See include/l1_alm.h for the contract.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+
+#include "internal.h"
+#include "plan.h"
+#include "steps.h"
+
+namespace l1 {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+template <class T>
+static T* dalloc(size_t count, std::vector<void*>& owned) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  const hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) {
+    set_error("hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " +
+              hipGetErrorString(e));
+    throw Fail{L1_ENOMEM};
+  }
+  owned.push_back(p);
+  return reinterpret_cast<T*>(p);
+}
+
+// FP64 scratch that lives only during plan construction
+struct Scratch {
+  std::vector<void*> v;
+  ~Scratch() {
+    for (void* p : v) (void)hipFree(p);
+  }
+  double* d(size_t n) { return dalloc<double>(n, v); }
+};
+
+static void check_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("no HIP device");
+    throw Fail{L1_ENODEVICE};
+  }
+  hipDeviceProp_t prop;
+  L1_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error(std::string("device is ") + prop.gcnArchName + ", libl1alm is built for gfx950");
+    throw Fail{L1_ENODEVICE};
+  }
+}
+
+// Spectral factor X = L^{-1} of S = L L^T (n x n, SPD), FP64, in `X` (ld n).
+static void inverse_factor(hipStream_t s, int n, double* S, double* X, Scratch& sc, int* info) {
+  double* dinv = sc.d((size_t)((n + 63) / 64) * 64 * 64);
+  double* work = sc.d((size_t)64 * n + (size_t)n * 64);
+  potrf64(s, n, S, n, dinv, info, work);
+  int h_info = 0;
+  L1_HIP(hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, s));
+  L1_HIP(hipStreamSynchronize(s));
+  if (h_info != 0) {
+    set_error("Gram matrix is not positive definite (Cholesky pivot " + std::to_string(h_info) +
+              " <= 0); the rows of the dictionary are linearly dependent");
+    throw Fail{L1_ENOTSPD};
+  }
+  lower_inverse64(s, n, S, n, dinv, X, n, work);
+}
+
+static void build_dalm(Plan* p, hipStream_t s, const double* A64, Scratch& sc, int* info) {
+  const int m = p->m, nd = p->nd, n = p->n;
+  double* P64 = sc.d((size_t)n * n);
+  if (p->split) {
+    if (nd <= m) {
+      // Woodbury: K = I + B^T B (nd x nd), H = K^{-1} = X^T X, T1 = B X^T
+      // P = [[I - X^T X, X^T T1^T], [T1 X, I - T1 T1^T]]
+      double* K = sc.d((size_t)nd * nd);
+      double* X = sc.d((size_t)nd * nd);
+      double* T1 = sc.d((size_t)m * nd);
+      gemm64(s, 'T', 'N', nd, nd, m, 1.0, A64, m, A64, m, 0.0, K, nd);
+      add_diag64(s, nd, K, nd, 1.0);
+      inverse_factor(s, nd, K, X, sc, info);
+      gemm64(s, 'N', 'T', m, nd, nd, 1.0, A64, m, X, nd, 0.0, T1, m);
+      gemm64(s, 'T', 'N', nd, nd, nd, -1.0, X, nd, X, nd, 0.0, P64, n);
+      add_diag64(s, nd, P64, n, 1.0);
+      gemm64(s, 'N', 'N', m, nd, nd, 1.0, T1, m, X, nd, 0.0, P64 + nd, n);
+      gemm64(s, 'T', 'T', nd, m, nd, 1.0, X, nd, T1, m, 0.0, P64 + (size_t)nd * n, n);
+      gemm64(s, 'N', 'T', m, m, nd, -1.0, T1, m, T1, m, 0.0, P64 + nd + (size_t)nd * n, n);
+      add_diag64(s, m, P64 + nd + (size_t)nd * n, n, 1.0);
+    } else {
+      // G = B B^T + I (m x m), G^{-1} = X^T X, T2 = X B
+      double* G = sc.d((size_t)m * m);
+      double* X = sc.d((size_t)m * m);
+      double* T2 = sc.d((size_t)m * nd);
+      gemm64(s, 'N', 'T', m, m, nd, 1.0, A64, m, A64, m, 0.0, G, m);
+      add_diag64(s, m, G, m, 1.0);
+      inverse_factor(s, m, G, X, sc, info);
+      gemm64(s, 'N', 'N', m, nd, m, 1.0, X, m, A64, m, 0.0, T2, m);
+      gemm64(s, 'T', 'N', nd, nd, m, 1.0, T2, m, T2, m, 0.0, P64, n);
+      gemm64(s, 'T', 'N', nd, m, m, 1.0, T2, m, X, m, 0.0, P64 + (size_t)nd * n, n);
+      gemm64(s, 'T', 'N', m, nd, m, 1.0, X, m, T2, m, 0.0, P64 + nd, n);
+      gemm64(s, 'T', 'N', m, m, m, 1.0, X, m, X, m, 0.0, P64 + nd + (size_t)nd * n, n);
+    }
+    // c = A^T G^{-1} b / beta is the block of P that multiplies the identity part
+    to_rowmajor_f32(s, n, m, P64 + (size_t)nd * n, n, p->Cop, p->m_pad, nullptr, nullptr);
+  } else {
+    // dense: G = A A^T + shift I = L L^T, X = L^{-1}, T2 = X A,
+    // P = T2^T T2, c-operator A^T G^{-1} = T2^T X, y-operator (A A^T)^{-1} A
+    double* G = sc.d((size_t)m * m);
+    double* X = sc.d((size_t)m * m);
+    double* T2 = sc.d((size_t)m * nd);
+    double* C64 = sc.d((size_t)nd * m);
+    gemm64(s, 'N', 'T', m, m, nd, 1.0, A64, m, A64, m, 0.0, G, m);
+    if (p->shift != 0.0) add_diag64(s, m, G, m, p->shift);
+    inverse_factor(s, m, G, X, sc, info);
+    gemm64(s, 'N', 'N', m, nd, m, 1.0, X, m, A64, m, 0.0, T2, m);
+    gemm64(s, 'T', 'N', nd, nd, m, 1.0, T2, m, T2, m, 0.0, P64, n);
+    gemm64(s, 'T', 'N', nd, m, m, 1.0, T2, m, X, m, 0.0, C64, nd);
+    to_rowmajor_f32(s, nd, m, C64, nd, p->Cop, p->m_pad, nullptr, nullptr);
+    double* Y64 = sc.d((size_t)m * nd);
+    if (p->shift == 0.0) {
+      gemm64(s, 'T', 'N', m, nd, m, 1.0, X, m, T2, m, 0.0, Y64, m);
+    } else {
+      double* G0 = sc.d((size_t)m * m);
+      double* X0 = sc.d((size_t)m * m);
+      double* T0 = sc.d((size_t)m * nd);
+      gemm64(s, 'N', 'T', m, m, nd, 1.0, A64, m, A64, m, 0.0, G0, m);
+      inverse_factor(s, m, G0, X0, sc, info);
+      gemm64(s, 'N', 'N', m, nd, m, 1.0, X0, m, A64, m, 0.0, T0, m);
+      gemm64(s, 'T', 'N', m, nd, m, 1.0, X0, m, T0, m, 0.0, Y64, m);
+    }
+    to_rowmajor_f32(s, m, nd, Y64, m, p->Yop, p->n_pad, nullptr, nullptr);
+  }
+  to_rowmajor_f32(s, n, n, P64, n, p->P32, p->n_pad, p->Phi, p->Plo);
+}
+
+static void build_palm(Plan* p, hipStream_t s, const double* A64, Scratch& sc) {
+  const int m = p->m, nd = p->nd;
+  double* M64 = sc.d((size_t)nd * nd);
+  gemm64(s, 'T', 'N', nd, nd, m, 1.0, A64, m, A64, m, 0.0, M64, nd);
+  to_rowmajor_f32(s, nd, nd, M64, nd, p->M32, p->nd_pad, p->Mhi, p->Mlo);
+  double* work = sc.d((size_t)2 * nd + 8);
+  p->Lf = power_lambda_max64(s, nd, M64, nd, work, 20000, 1e-13);
+}
+
+Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
+  L1_REQUIRE(d != nullptr && A_dev != nullptr, "desc and A must be non-NULL");
+  L1_REQUIRE(d->m >= 1 && d->n_dict >= 0 && d->lda >= d->m, "bad sizes: need m >= 1, n_dict >= 0, lda >= m");
+  L1_REQUIRE(d->max_batch >= 1, "max_batch must be >= 1");
+  L1_REQUIRE(d->problem >= 0 && d->problem <= 2, "unknown problem");
+  L1_REQUIRE(d->structure == L1_DENSE || d->structure == L1_CAB, "unknown structure");
+  L1_REQUIRE(d->method == L1_DALM || d->method == L1_PALM, "unknown method");
+  L1_REQUIRE(d->precision >= 0 && d->precision <= 2, "unknown precision");
+  L1_REQUIRE(!(d->structure == L1_CAB && d->problem != L1_P1),
+             "QP_lambda and P_{1,2} are defined on a dense dictionary (structure L1_DENSE)");
+  L1_REQUIRE(d->problem != L1_QPLAMBDA || d->lambda > 0, "QP_lambda needs lambda > 0");
+  L1_REQUIRE(!(d->method == L1_DALM && d->problem == L1_QPLAMBDA && !(d->beta > 0)),
+             "DALM on QP_lambda needs beta > 0 (it enters the factor A A^T + lambda/beta I)");
+  L1_REQUIRE(d->structure == L1_CAB || d->n_dict >= 1, "a dense dictionary needs n_dict >= 1");
+  L1_REQUIRE((long)d->m * d->n_dict < (1L << 31) && d->m + d->n_dict < (1 << 20), "dictionary too large");
+  check_device();
+
+  std::unique_ptr<Plan> p(new Plan());
+  p->d = *d;
+  L1_HIP(hipGetDevice(&p->dev));
+  const int m = d->m, nd = d->n_dict;
+  p->m = m;
+  p->nd = nd;
+  p->split = (d->structure == L1_CAB || d->problem == L1_P12) ? 1 : 0;
+  p->n = p->split ? nd + m : nd;
+  p->m_pad = round_up(m, KPAD);
+  p->nd_pad = round_up(nd > 0 ? nd : 1, KPAD);
+  p->n_pad = round_up(p->n, KPAD);
+  p->N_pad = round_up(d->max_batch, TILE);
+  p->e0 = (d->problem == L1_P12) ? nd : (1 << 30);
+  p->n_l1 = (d->problem == L1_P12) ? nd : p->n;
+  p->shift = (d->problem == L1_QPLAMBDA && d->method == L1_DALM) ? d->lambda / d->beta : 0.0;
+  const bool low = d->precision != L1_FP32;
+  auto& o = p->owned;
+
+  // dictionary copies (FP32)
+  p->A = dalloc<float>((size_t)m * (nd > 0 ? nd : 1), o);
+  if (nd > 0)
+    L1_HIP(hipMemcpy2DAsync(p->A, sizeof(float) * m, A_dev, sizeof(float) * d->lda,
+                            sizeof(float) * m, nd, hipMemcpyDeviceToDevice, s));
+  p->Acol = dalloc<float>((size_t)p->nd_pad * p->m_pad, o);
+  p->Arow = dalloc<float>((size_t)p->m_pad * p->nd_pad, o);
+  L1_HIP(hipMemsetAsync(p->Acol, 0, sizeof(float) * p->nd_pad * p->m_pad, s));
+  L1_HIP(hipMemsetAsync(p->Arow, 0, sizeof(float) * p->m_pad * p->nd_pad, s));
+  // Acol[i*m_pad + k] = A[k + i*m]: row i is column i of A
+  if (nd > 0)
+    L1_HIP(hipMemcpy2DAsync(p->Acol, sizeof(float) * p->m_pad, p->A, sizeof(float) * m,
+                            sizeof(float) * m, nd, hipMemcpyDeviceToDevice, s));
+
+  Scratch sc;
+  double* A64 = sc.d((size_t)m * (nd > 0 ? nd : 1));
+  f32_to_f64(s, m, nd, p->A, m, A64, m);
+  // Arow[r*nd_pad + k] = A[r + k*m]
+  to_rowmajor_f32(s, m, nd, A64, m, p->Arow, p->nd_pad, nullptr, nullptr);
+  int* info = reinterpret_cast<int*>(sc.d(1));
+
+  if (d->method == L1_DALM) {
+    const size_t nn = (size_t)p->n_pad * p->n_pad;
+    p->P32 = dalloc<float>(nn, o);
+    L1_HIP(hipMemsetAsync(p->P32, 0, sizeof(float) * nn, s));
+    if (low) {
+      p->Phi = dalloc<uint16_t>(nn, o);
+      p->Plo = dalloc<uint16_t>(nn, o);
+      L1_HIP(hipMemsetAsync(p->Phi, 0, sizeof(uint16_t) * nn, s));
+      L1_HIP(hipMemsetAsync(p->Plo, 0, sizeof(uint16_t) * nn, s));
+    }
+    p->Cop = dalloc<float>((size_t)p->n_pad * p->m_pad, o);
+    L1_HIP(hipMemsetAsync(p->Cop, 0, sizeof(float) * p->n_pad * p->m_pad, s));
+    if (!p->split) {
+      p->Yop = dalloc<float>((size_t)p->m_pad * p->n_pad, o);
+      L1_HIP(hipMemsetAsync(p->Yop, 0, sizeof(float) * p->m_pad * p->n_pad, s));
+    }
+    build_dalm(p.get(), s, A64, sc, info);
+  } else {
+    const size_t nn = (size_t)p->nd_pad * p->nd_pad;
+    p->M32 = dalloc<float>(nn, o);
+    L1_HIP(hipMemsetAsync(p->M32, 0, sizeof(float) * nn, s));
+    if (low) {
+      p->Mhi = dalloc<uint16_t>(nn, o);
+      p->Mlo = dalloc<uint16_t>(nn, o);
+      L1_HIP(hipMemsetAsync(p->Mhi, 0, sizeof(uint16_t) * nn, s));
+      L1_HIP(hipMemsetAsync(p->Mlo, 0, sizeof(uint16_t) * nn, s));
+    }
+    if (nd > 0) build_palm(p.get(), s, A64, sc);
+  }
+
+  // per-solve workspace
+  const size_t Np = p->N_pad;
+  const int rows = (d->method == L1_DALM) ? p->n_pad : std::max(p->nd_pad, p->m_pad);
+  p->lds = rows;
+  const size_t st = (size_t)rows * Np;
+  p->W = dalloc<float>(st, o);
+  p->V = dalloc<float>(st, o);
+  p->C = dalloc<float>(st, o);
+  p->Z[0] = dalloc<float>(st, o);
+  p->Z[1] = dalloc<float>(st, o);
+  for (int b = 0; b < 2; ++b) {
+    p->Uf[b] = dalloc<float>(st, o);
+    L1_HIP(hipMemsetAsync(p->Uf[b], 0, sizeof(float) * st, s));
+  }
+  p->bb = dalloc<float>((size_t)p->m_pad * Np, o);
+  p->aux = dalloc<float>((size_t)p->m_pad * Np * 4, o);
+  p->pen = dalloc<float>(Np, o);
+  p->ipen = dalloc<float>(Np, o);
+  p->zscale = dalloc<float>(Np, o);
+  p->tscal = dalloc<float>(Np * 4, o);
+  const int ntiles = rows / TILE;
+  p->ntiles = ntiles;
+  p->partial = dalloc<float>((size_t)ntiles * NPART * Np, o);
+  p->ints = dalloc<int>(Np * 8 + 256, o);
+  p->stat = dalloc<long long>(8, o);
+  p->kkt_rbuf = dalloc<double>((size_t)m * Np, o);
+  L1_HIP(hipHostMalloc((void**)&p->h_total, sizeof(int) * 4, 0));
+  L1_HIP(hipStreamSynchronize(s));
+  return p.release();
+}
+
+void destroy_plan(Plan* p) {
+  if (!p) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->dev);
+  (void)hipDeviceSynchronize();
+  for (void* q : p->owned) (void)hipFree(q);
+  for (void* q : p->tape) (void)hipFree(q);
+  if (p->h_total) (void)hipHostFree(p->h_total);
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete p;
+}
+
+}  // namespace l1
+
+using namespace l1;
+
+extern "C" {
+
+const char* l1_alm_last_error(void) { return g_err.c_str(); }
+
+int l1_alm_plan(const l1_alm_desc* desc, const float* A_dev, void* stream, l1_alm_plan_t* out) {
+  try {
+    L1_REQUIRE(out != nullptr, "out must be non-NULL");
+    *out = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    Plan* p = create_plan(desc, A_dev, reinterpret_cast<hipStream_t>(stream));
+    p->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = reinterpret_cast<l1_alm_plan_t>(p);
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
+int l1_alm_destroy(l1_alm_plan_t plan) {
+  destroy_plan(reinterpret_cast<Plan*>(plan));
+  return L1_OK;
+}
+
+int l1_alm_solve(l1_alm_plan_t plan, const float* b_dev, int ldb, int N, const float* eps_dev,
+                 float tol, int max_iter, const float* w0_dev, const float* y0_dev, float* x_dev,
+                 int ldx, float* e_dev, int lde, float* y_dev, int ldy, int* iters_dev,
+                 int* status_dev, void* stream) {
+  try {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    L1_REQUIRE(p != nullptr, "plan is NULL");
+    SolveArgs a{b_dev, ldb, N, eps_dev, tol, max_iter, w0_dev, y0_dev, x_dev, ldx, e_dev, lde,
+                y_dev, ldy, iters_dev, status_dev, reinterpret_cast<hipStream_t>(stream)};
+    if (p->d.method == L1_DALM) solve_dalm(p, a);
+    else solve_palm(p, a);
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
+int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N, const float* eps_dev,
+               const float* x_dev, int ldx, const float* e_dev, int lde, const float* y_dev,
+               int ldy, double* report_dev, void* stream) {
+  try {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    L1_REQUIRE(p != nullptr, "plan is NULL");
+    L1_REQUIRE(N >= 0 && N <= p->N_pad, "N out of range (max_batch)");
+    if (N == 0) return L1_OK;
+    L1_REQUIRE(b_dev && x_dev && report_dev, "b, x and report must be non-NULL");
+    L1_REQUIRE(ldb >= p->m && ldx >= std::max(p->nd, 1), "bad leading dimension");
+    const int prob = p->d.problem;
+    L1_REQUIRE(prob == L1_QPLAMBDA || y_dev != nullptr, "y is needed for P1 and P_{1,2}");
+    L1_REQUIRE(prob != L1_P12 || eps_dev != nullptr, "P_{1,2} needs eps");
+    L1_REQUIRE(p->d.structure != L1_CAB || e_dev != nullptr, "CAB needs e");
+    if (y_dev) L1_REQUIRE(ldy >= p->m, "bad ldy");
+    if (e_dev) L1_REQUIRE(lde >= p->m, "bad lde");
+    const int split = (p->d.structure == L1_CAB) ? 1 : 0;
+    kkt64(reinterpret_cast<hipStream_t>(stream), prob, p->m, p->nd, split, p->A, p->m, b_dev,
+          ldb, x_dev, ldx, e_dev, lde, y_dev, ldy, eps_dev, p->d.lambda, N, p->kkt_rbuf,
+          report_dev);
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
+int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n) {
+  try {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    L1_REQUIRE(p != nullptr && out != nullptr, "plan and out must be non-NULL");
+    p->last_stats[10] = p->plan_ms;
+    for (int i = 0; i < n && i < 14; ++i) out[i] = p->last_stats[i];
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int l1_alm_backward(l1_alm_plan_t plan, const float* gx_dev, const float* ge_dev, float* gb_dev,
+                    float* gA_dev, void* stream) {
+  try {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    L1_REQUIRE(p != nullptr, "plan is NULL");
+    backward_dalm(p, gx_dev, ge_dev, gb_dev, gA_dev, reinterpret_cast<hipStream_t>(stream));
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
+}  // extern "C"

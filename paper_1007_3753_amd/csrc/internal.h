@@ -1,0 +1,132 @@
+// Internal declarations shared by the translation units of libl1alm.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/l1_alm.h"
+
+namespace l1 {
+
+constexpr int TILE = 64;          // output tile edge of the iteration GEMMs
+constexpr int KPAD = 64;          // reduction dimension padding
+// per-column partial sums written by the DALM epilogue: ||dw||^2, ||w||^2,
+// ||w||_1, sum |w|(1 - sign(w) v) (the l1/duality gap), ||s_ball||^2
+constexpr int NPART = 5;
+
+inline int round_up(int x, int r) { return (x + r - 1) / r * r; }
+
+// ---- error plumbing ------------------------------------------------------
+void set_error(const std::string& msg);
+struct Fail {
+  int code;
+};
+#define L1_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::l1::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      throw ::l1::Fail{L1_EHIP};                                                  \
+    }                                                                             \
+  } while (0)
+#define L1_REQUIRE(cond, msg)                                                     \
+  do {                                                                            \
+    if (!(cond)) {                                                                \
+      ::l1::set_error(msg);                                                       \
+      throw ::l1::Fail{L1_EINVAL};                                                \
+    }                                                                             \
+  } while (0)
+
+// ---- FP64 dense kernels (plan set-up and certificates) -------------------
+// C = alpha op(A) op(B) + beta C; column-major; ta/tb 'N' or 'T'.
+void gemm64(hipStream_t s, char ta, char tb, int M, int N, int K, double alpha,
+            const double* A, int lda, const double* B, int ldb, double beta,
+            double* C, int ldc);
+void add_diag64(hipStream_t s, int n, double* A, int lda, double c);
+void f32_to_f64(hipStream_t s, int rows, int cols, const float* src, int lds,
+                double* dst, int ldd);
+// In-place lower Cholesky of the SPD matrix A (n x n); the strictly upper part
+// is zeroed.  Diagonal-block inverses go to diaginv (64*64 per block).
+// *info_dev receives 0, or 1 + the index of the first non-positive pivot.
+void potrf64(hipStream_t s, int n, double* A, int lda, double* diaginv, int* info_dev,
+             double* work);
+// X = L^{-1} for the factor produced by potrf64.
+void lower_inverse64(hipStream_t s, int n, const double* L, int lda,
+                     const double* diaginv, double* X, int ldx, double* work);
+// Largest eigenvalue of the symmetric PSD matrix M (n x n) by power iteration.
+double power_lambda_max64(hipStream_t s, int n, const double* M, int ldm, double* work,
+                          int max_iter, double rtol);
+
+// Operator layout helpers: dst[i*ldd + k] = src[i + k*lds]  (i < rows, k < cols)
+// written as FP32, and optionally as a BF16 hi/lo split.
+void to_rowmajor_f32(hipStream_t s, int rows, int cols, const double* src, int lds,
+                     float* dst, int ldd, uint16_t* hi, uint16_t* lo);
+// dst[i*ldd + k] = src[k + i*lds]: a plain FP32 copy of the transpose.
+void transpose_f64_to_f32(hipStream_t s, int rows, int cols, const double* src, int lds,
+                          float* dst, int ldd);
+
+// FP64 optimality report, one workgroup per instance.
+void kkt64(hipStream_t s, int problem, int m, int nd, int split, const float* A, int lda,
+           const float* b, int ldb, const float* x, int ldx, const float* e, int lde,
+           const float* y, int ldy, const float* eps, double lambda, int N, double* rbuf,
+           double* report);
+
+// ---- iteration kernels ---------------------------------------------------
+// Arithmetic of a product.  Phase p of an instance selects PHASE_PREC[p].
+enum Prec { PREC_BF16 = 0, PREC_BF16X3 = 1, PREC_F32 = 2 };
+enum Epi { EPI_STORE = 0, EPI_DALM = 1, EPI_FISTA = 2 };
+constexpr int NPHASE = 3;   // phase index == Prec
+
+struct GemmArgs {
+  // A-operand: M x K, element (i, k) at A[i*lda + k] (rows padded to TILE,
+  // K padded to KPAD with zeros).  FP32 copy (A32) and BF16 hi/lo split
+  // (Ahi, Alo; may be null when no BF16 phase runs).
+  const float* A32;
+  const uint16_t* Ahi;
+  const uint16_t* Alo;
+  int lda;
+  // B-operand: K x ncols FP32, element (k, col) at B[col*ldb + k].
+  const float* B;
+  int ldb;
+  int M;   // padded rows (multiple of TILE)
+  int K;   // padded reduction length (multiple of KPAD)
+  // Columns: tile slot s holds column slot_col[s] (-1 = idle).  Slots are
+  // grouped by phase: phase p owns [phase_off[p], phase_off[p+1]), each range
+  // a multiple of TILE.  With slot_col == null, slot s < n_cols is column s
+  // and every tile uses `prec`.
+  const int* slot_col;
+  const int* phase_off;
+  int n_cols;
+  int prec;
+  // ---- epilogue -----------------------------------------------------------
+  int m_true;              // rows < m_true are written (EPI_STORE)
+  float* out;              // EPI_STORE: out[col*ldo + i]; EPI_FISTA: next point z
+  int ldo;
+  const float* col_scale;  // EPI_STORE: multiply by col_scale[col] (or 1)
+  // EPI_DALM / EPI_FISTA state, all column-major with leading dimension lds
+  int lds;
+  float* V;             // DALM: v = A^T y              | FISTA: current point z (read)
+  float* W;             // DALM: w = [x; e]             | FISTA: w (last shrink output)
+  const float* C;       // DALM: c = A^T G^{-1} b/beta  | FISTA: h = A^T (b - e + theta/xi)
+  const float* beta;    // DALM: beta per column        | FISTA: xi per column
+  float* U;             // DALM: next B-operand u (FP32)
+  float* partial;       // partial[(tile*NPART + q)*ldp + col]
+  int ldp;
+  int n_l1;             // DALM: rows < n_l1 carry the l1 norm (gap sums)
+  int e0;               // DALM P_{1,2}: rows >= e0 are the eps-ball block (block prox)
+  const float* zscale;  // DALM P_{1,2}: block-prox scale of the previous z-step per column
+  float inv_L;          // FISTA: 1/L
+  float gamma;          // FISTA: (t_l - 1)/t_{l+1}
+};
+
+// Number of column tiles a launch must cover for up to n columns split over
+// the phases (each phase range is padded to a multiple of TILE).
+inline int col_tiles_for(int n) { return (n + TILE - 1) / TILE + NPHASE - 1; }
+void launch_gemm(hipStream_t s, int epi, const GemmArgs& a, int n_col_tiles);
+
+// ---- small per-iteration kernels ---------------------------------------
+void fill_iota(hipStream_t s, int* p, int n);
+void fill_f32(hipStream_t s, float* p, long n, float v);
+
+}  // namespace l1

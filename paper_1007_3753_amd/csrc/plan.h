@@ -1,0 +1,83 @@
+// The plan object and the solver drivers.
+#pragma once
+#include "internal.h"
+
+namespace l1 {
+
+struct Plan {
+  l1_alm_desc d{};
+  int dev = 0;
+  int m = 0, nd = 0, n = 0, split = 0;
+  int m_pad = 0, nd_pad = 0, n_pad = 0, N_pad = 0;
+  int e0 = 0, n_l1 = 0;
+  int lds = 0, ntiles = 0;
+  double shift = 0.0;   // lambda / beta in the DALM factor for QP_lambda
+  double Lf = 0.0;      // PALM: ||A^T A||_2
+  std::vector<void*> owned;
+  // dictionary (FP32)
+  float* A = nullptr;     // m x nd, ld m
+  float* Acol = nullptr;  // nd_pad x m_pad, row i = column i of A
+  float* Arow = nullptr;  // m_pad x nd_pad, row r = row r of A
+  // DALM operators (rows K-contiguous, zero padded)
+  float* P32 = nullptr;   // n_pad x n_pad
+  uint16_t* Phi = nullptr;
+  uint16_t* Plo = nullptr;
+  float* Cop = nullptr;   // n_pad x m_pad
+  float* Yop = nullptr;   // m_pad x n_pad (dense only)
+  // PALM operators
+  float* M32 = nullptr;   // nd_pad x nd_pad
+  uint16_t* Mhi = nullptr;
+  uint16_t* Mlo = nullptr;
+  // workspace, column-major with leading dimension lds, N_pad columns
+  float* W = nullptr;
+  float* V = nullptr;
+  float* C = nullptr;
+  float* Z[2] = {nullptr, nullptr};
+  float* Uf[2] = {nullptr, nullptr};  // ping-pong B-operand of the iteration (FP32)
+  float* bb = nullptr;    // m_pad x N_pad copy of b
+  float* aux = nullptr;   // 4 x (m_pad x N_pad) scratch
+  float* pen = nullptr;   // beta (DALM) or xi (PALM) per column
+  float* ipen = nullptr;  // its reciprocal
+  float* zscale = nullptr;
+  float* tscal = nullptr;
+  float* partial = nullptr;
+  int* ints = nullptr;    // lists and counters
+  long long* stat = nullptr;
+  double* kkt_rbuf = nullptr;
+  int* h_total = nullptr; // pinned
+  double last_stats[14] = {0};
+  double plan_ms = 0.0;
+  // tape of the last recorded fixed-count solve
+  std::vector<void*> tape;
+  int tape_N = 0, tape_K = 0, tape_every = 0;
+  float* tape_b = nullptr;
+};
+
+struct SolveArgs {
+  const float* b;
+  int ldb;
+  int N;
+  const float* eps;
+  float tol;
+  int max_iter;
+  const float* w0;
+  const float* y0;
+  float* x;
+  int ldx;
+  float* e;
+  int lde;
+  float* y;
+  int ldy;
+  int* iters;
+  int* status;
+  hipStream_t s;
+};
+
+Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s);
+void destroy_plan(Plan* p);
+void solve_dalm(Plan* p, const SolveArgs& a);
+void solve_palm(Plan* p, const SolveArgs& a);
+void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* gA,
+                   hipStream_t s);
+
+}  // namespace l1

@@ -1,0 +1,394 @@
+// Solve drivers.  All work of a solve runs on a plan-private stream that is
+// ordered after the caller's stream at entry and before it at exit, so the
+// iteration blocks can be captured into HIP graphs whatever stream the caller
+// uses.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "plan.h"
+#include "steps.h"
+
+namespace l1 {
+
+namespace {
+
+struct StreamGuard {
+  hipStream_t user, own;
+  hipEvent_t ev;
+  StreamGuard(hipStream_t u) : user(u) {
+    L1_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    L1_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    L1_HIP(hipEventRecord(ev, user));
+    L1_HIP(hipStreamWaitEvent(own, ev, 0));
+  }
+  ~StreamGuard() {
+    (void)hipEventRecord(ev, own);
+    (void)hipStreamWaitEvent(user, ev, 0);
+    (void)hipStreamSynchronize(own);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(own);
+  }
+};
+
+Lists lists_of(Plan* p) {
+  const int Np = p->N_pad;
+  int* q = p->ints;
+  Lists L;
+  L.state = q;
+  L.iters = q + Np;
+  L.status = q + 2 * Np;
+  L.slot_col = q + 3 * Np;                         // Np + NPHASE*TILE entries
+  L.phase_off = q + 4 * Np + NPHASE * TILE;        // NPHASE + 1 entries
+  L.n_total = L.phase_off + NPHASE + 1;
+  return L;
+}
+
+bool graphs_enabled() {
+  const char* e = std::getenv("L1ALM_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+void check_common(Plan* p, const SolveArgs& a) {
+  L1_REQUIRE(a.N >= 0 && a.N <= p->d.max_batch, "N must be in [0, max_batch]");
+  if (a.N == 0) return;
+  L1_REQUIRE(a.b != nullptr && a.x != nullptr, "b and x must be non-NULL");
+  L1_REQUIRE(a.ldb >= p->m, "ldb < m");
+  L1_REQUIRE(a.ldx >= std::max(p->nd, 1), "ldx < n_dict");
+  L1_REQUIRE(a.e == nullptr || a.lde >= p->m, "lde < m");
+  L1_REQUIRE(a.y == nullptr || a.ldy >= p->m, "ldy < m");
+  L1_REQUIRE(p->d.problem != L1_P12 || a.eps != nullptr, "P_{1,2} needs eps (N radii)");
+  L1_REQUIRE(a.max_iter != 0, "max_iter must be nonzero");
+  L1_REQUIRE(std::isfinite(a.tol) && a.tol >= 0.0f, "tol must be finite and >= 0");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Precision schedule: the first phase, the final phase and the floors of the
+// stopping test (where the rounding of the products stalls it).
+static void dalm_phases(int precision, bool fixed, int* first, int* last) {
+  if (precision == L1_FP32) *first = *last = PREC_F32;
+  else if (precision == L1_BF16X3) *first = *last = PREC_BF16X3;
+  else {
+    *first = PREC_BF16;
+    *last = PREC_BF16X3;
+  }
+  (void)fixed;
+}
+
+void solve_dalm(Plan* p, const SolveArgs& a) {
+  check_common(p, a);
+  if (a.N == 0) return;
+  const auto t_start = std::chrono::steady_clock::now();
+  const bool fixed = a.max_iter < 0;
+  L1_REQUIRE(!(fixed && p->d.record_tape) || p->d.structure == L1_CAB,
+             "recording a tape is supported for the cross-and-bouquet DALM");
+  const int cap = fixed ? -a.max_iter : a.max_iter;
+  StreamGuard sg(a.s);
+  hipStream_t s = sg.own;
+  const int N = a.N, m = p->m, nd = p->nd, n = p->n, lds = p->lds;
+  const int ntc = (N + TILE - 1) / TILE;
+  const int ctiles = col_tiles_for(N);
+  const bool p12 = p->d.problem == L1_P12;
+  int first, last;
+  dalm_phases(p->d.precision, fixed, &first, &last);
+  const float sw = (p->d.refine_switch > 0) ? (float)p->d.refine_switch : 3e-3f;
+
+  // b, penalties, c = A^T G^{-1} b / beta
+  L1_HIP(hipMemsetAsync(p->bb, 0, sizeof(float) * p->m_pad * N, s));
+  L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * p->m_pad, a.b, sizeof(float) * a.ldb,
+                          sizeof(float) * m, N, hipMemcpyDeviceToDevice, s));
+  penalties(s, N, m, p->bb, p->m_pad, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0, p->pen,
+            p->ipen);
+  {
+    GemmArgs g{};
+    g.A32 = p->Cop;
+    g.lda = p->m_pad;
+    g.B = p->bb;
+    g.ldb = p->m_pad;
+    g.M = p->n_pad;
+    g.K = p->m_pad;
+    g.n_cols = N;
+    g.prec = PREC_F32;
+    g.m_true = p->n_pad;
+    g.out = p->C;
+    g.ldo = lds;
+    g.col_scale = p->ipen;
+    launch_gemm(s, EPI_STORE, g, ntc);
+  }
+  float* eps = nullptr;
+  if (p12) {
+    eps = p->tscal;
+    L1_HIP(hipMemcpyAsync(eps, a.eps, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
+  }
+  // initial state (Algorithm 2 input: w = 0, y = 0, or a warm start)
+  L1_HIP(hipMemsetAsync(p->W, 0, sizeof(float) * (size_t)lds * N, s));
+  L1_HIP(hipMemsetAsync(p->V, 0, sizeof(float) * (size_t)lds * N, s));
+  if (a.w0) copy_in(s, n, N, a.w0, n, p->W, lds, 0);
+  if (a.y0) {
+    L1_HIP(hipMemsetAsync(p->aux, 0, sizeof(float) * p->m_pad * N, s));
+    copy_in(s, m, N, a.y0, m, p->aux, p->m_pad, 0);
+    if (nd > 0) {
+      GemmArgs g{};
+      g.A32 = p->Acol;
+      g.lda = p->m_pad;
+      g.B = p->aux;
+      g.ldb = p->m_pad;
+      g.M = p->nd_pad;
+      g.K = p->m_pad;
+      g.n_cols = N;
+      g.prec = PREC_F32;
+      g.m_true = nd;
+      g.out = p->V;
+      g.ldo = lds;
+      launch_gemm(s, EPI_STORE, g, ntc);
+    }
+    if (p->split) copy_in(s, m, N, a.y0, m, p->V, lds, nd);
+  }
+  {
+    DalmInit di{};
+    di.n = n;
+    di.n_pad = p->n_pad;
+    di.lds = lds;
+    di.e0 = p12 ? nd : (1 << 30);
+    di.V = p->V;
+    di.W = p->W;
+    di.beta = p->pen;
+    di.eps = eps;
+    di.zscale = p->zscale;
+    di.U = p->Uf[0];
+    dalm_init_u(s, N, di);
+  }
+  const Lists L = lists_of(p);
+  init_lists(s, N, first, L, p->stat);
+
+  // tape: checkpoints of (W, V) every k iterations of a fixed-count solve
+  const bool tape = fixed && p->d.record_tape;
+  const int every = p->d.checkpoint_every > 0 ? p->d.checkpoint_every : 10;
+  if (tape) {
+    for (void* q : p->tape) (void)hipFree(q);
+    p->tape.clear();
+    const int nck = (cap + every - 1) / every;  // states at iterations 0, k, 2k, ... < cap
+    for (int i = 0; i < 2 * nck + 1; ++i) {
+      void* q = nullptr;
+      L1_HIP(hipMalloc(&q, sizeof(float) * (size_t)lds * N));
+      p->tape.push_back(q);
+    }
+    p->tape_N = N;
+    p->tape_K = cap;
+    p->tape_every = every;
+    p->tape_b = reinterpret_cast<float*>(p->tape.back());
+    L1_HIP(hipMemcpyAsync(p->tape_b, p->bb, sizeof(float) * p->m_pad * N,
+                          hipMemcpyDeviceToDevice, s));
+  }
+
+  GemmArgs it{};
+  it.A32 = p->P32;
+  it.Ahi = p->Phi;
+  it.Alo = p->Plo;
+  it.lda = p->n_pad;
+  it.ldb = lds;
+  it.M = p->n_pad;
+  it.K = p->n_pad;
+  it.slot_col = L.slot_col;
+  it.phase_off = L.phase_off;
+  it.n_cols = N;
+  it.lds = lds;
+  it.V = p->V;
+  it.W = p->W;
+  it.C = p->C;
+  it.beta = p->pen;
+  it.partial = p->partial;
+  it.ldp = p->N_pad;
+  it.n_l1 = p->n_l1;
+  it.e0 = p12 ? nd : (1 << 30);
+  it.zscale = p12 ? p->zscale : nullptr;
+  DalmCheck ck{};
+  ck.N = N;
+  ck.partial = p->partial;
+  ck.ldp = p->N_pad;
+  ck.ntiles = p->ntiles;
+  ck.tol = fixed ? -1.0f : a.tol;
+  ck.floor[PREC_BF16] = 1.0f;
+  ck.floor[PREC_BF16X3] = 4e-6f;
+  ck.floor[PREC_F32] = 2e-6f;
+  ck.sw = sw;
+  ck.final_phase = last;
+  ck.L = L;
+  ck.eps = eps;
+  ck.beta = p->pen;
+  ck.zscale = p12 ? p->zscale : nullptr;
+  ck.stat = p->stat;
+  P12Fix fx{};
+  fx.n = n;
+  fx.e0 = nd;
+  fx.lds = lds;
+  fx.slot_col = L.slot_col;
+  fx.phase_off = L.phase_off;
+  fx.V = p->V;
+  fx.W = p->W;
+  fx.beta = p->pen;
+  fx.zscale = p->zscale;
+
+  constexpr int BLK = 16;  // iterations per graph replay / host poll (even)
+  const bool timing = p->d.time_kernels != 0;
+  std::vector<hipEvent_t> ev;
+  if (timing) {
+    ev.resize(2 * BLK);
+    for (auto& e : ev) L1_HIP(hipEventCreate(&e));
+  }
+  auto one_iter = [&](int t, int cur) {
+    it.B = p->Uf[cur];
+    it.U = p->Uf[1 - cur];
+    if (timing) L1_HIP(hipEventRecord(ev[2 * t], s));
+    launch_gemm(s, EPI_DALM, it, ctiles);
+    if (timing) L1_HIP(hipEventRecord(ev[2 * t + 1], s));
+    dalm_check(s, ck);
+    if (p12) {
+      fx.U = p->Uf[1 - cur];
+      p12_fix(s, ntc * TILE + NPHASE * TILE, fx);
+    }
+  };
+
+  // events recorded inside a captured graph cannot be timed, so timing runs uncaptured
+  bool use_graph = graphs_enabled() && !tape && !timing && cap >= 4 * BLK;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph) {
+    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      try {
+        for (int t = 0; t < BLK; ++t) one_iter(t, t & 1);
+      } catch (const Fail&) {
+        ok = false;
+      }
+      hipError_t e = hipStreamEndCapture(s, &graph);
+      ok = ok && e == hipSuccess &&
+           hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      if (graph) (void)hipGraphDestroy(graph);
+      gexec = nullptr;
+      graph = nullptr;
+      use_graph = false;
+    }
+  }
+  long long hstat[8] = {0}, prev_any = 0;
+  double timed_ms = 0.0;
+  long long timed_n = 0;
+  int done = 0, cur = 0;
+  try {
+    while (done < cap) {
+      const int blk = std::min(BLK, cap - done);
+      if (tape) {
+        for (int t = 0; t < blk; ++t) {
+          const int k = done + t;
+          if (k % every == 0) {
+            const int ci = k / every;
+            L1_HIP(hipMemcpyAsync(p->tape[2 * ci], p->W, sizeof(float) * (size_t)lds * N,
+                                  hipMemcpyDeviceToDevice, s));
+            L1_HIP(hipMemcpyAsync(p->tape[2 * ci + 1], p->V, sizeof(float) * (size_t)lds * N,
+                                  hipMemcpyDeviceToDevice, s));
+          }
+          one_iter(t, cur);
+          cur ^= 1;
+        }
+      } else if (gexec && blk == BLK && cur == 0) {
+        L1_HIP(hipGraphLaunch(gexec, s));
+      } else {
+        for (int t = 0; t < blk; ++t) {
+          one_iter(t, cur);
+          cur ^= 1;
+        }
+      }
+      done += blk;
+      L1_HIP(hipMemcpyAsync(p->h_total, L.n_total, sizeof(int), hipMemcpyDeviceToHost, s));
+      if (timing)
+        L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
+      L1_HIP(hipStreamSynchronize(s));
+      if (timing) {
+        // launches of this block that had work come first (work only shrinks)
+        const long long any = hstat[6];
+        const int with_work = (int)std::min<long long>(any - prev_any, blk);
+        prev_any = any;
+        for (int t = 0; t < with_work; ++t) {
+          float ms = 0.0f;
+          L1_HIP(hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]));
+          timed_ms += ms;
+          ++timed_n;
+        }
+      }
+      if (!fixed && *p->h_total == 0) break;
+    }
+  } catch (...) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : ev) (void)hipEventDestroy(e);
+    throw;
+  }
+  if (gexec) L1_HIP(hipGraphExecDestroy(gexec));
+  if (graph) L1_HIP(hipGraphDestroy(graph));
+  for (auto e : ev) L1_HIP(hipEventDestroy(e));
+
+  // outputs
+  copy_block(s, nd, N, p->W, lds, 0, a.x, a.ldx);
+  if (p->split && a.e) copy_block(s, m, N, p->W, lds, nd, a.e, a.lde);
+  if (a.y) {
+    if (p->split) {
+      copy_block(s, m, N, p->V, lds, nd, a.y, a.ldy);
+    } else {
+      GemmArgs g{};
+      g.A32 = p->Yop;
+      g.lda = p->n_pad;
+      g.B = p->V;
+      g.ldb = lds;
+      g.M = p->m_pad;
+      g.K = p->n_pad;
+      g.n_cols = N;
+      g.prec = PREC_F32;
+      g.m_true = m;
+      g.out = a.y;
+      g.ldo = a.ldy;
+      launch_gemm(s, EPI_STORE, g, ntc);
+    }
+  }
+  finish_status(s, N, fixed ? cap : 0, L.iters, L.status, a.iters, a.status);
+  L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
+  L1_HIP(hipStreamSynchronize(s));
+  // stats: header order FP32, BF16, split; internal phase order BF16, split, FP32
+  const int map[3] = {PREC_F32, PREC_BF16, PREC_BF16X3};
+  for (int i = 0; i < 14; ++i) p->last_stats[i] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    p->last_stats[i] = (double)hstat[map[i]];
+    p->last_stats[3 + i] = (double)hstat[3 + map[i]];
+  }
+  p->last_stats[6] = timed_ms;
+  p->last_stats[7] = (double)timed_n;
+  p->last_stats[8] = (double)std::min(done, cap);
+  p->last_stats[9] =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+}
+
+void solve_palm(Plan* p, const SolveArgs& a) {
+  check_common(p, a);
+  set_error("PALM is not available in this build");
+  throw Fail{L1_EINVAL};
+}
+
+void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* gA,
+                   hipStream_t s) {
+  (void)gx; (void)ge; (void)gb; (void)gA; (void)s;
+  if (p->tape.empty()) {
+    set_error("no recorded tape: solve with max_iter < 0 and desc.record_tape = 1 first");
+    throw Fail{L1_ENOTAPE};
+  }
+  set_error("backward is not available in this build");
+  throw Fail{L1_EINVAL};
+}
+
+}  // namespace l1

@@ -1,0 +1,70 @@
+// Declarations of the small per-solve / per-iteration kernels (steps.hip).
+#pragma once
+#include "internal.h"
+
+namespace l1 {
+
+// Per-instance state of a solve: 0 = BF16 products, 1 = split-BF16 products,
+// 2 = FP32 products (the phase index equals the Prec of its products),
+// 3 = finished.  The active instances of the next iteration are listed in
+// slot_col, grouped by phase: phase p owns slots [phase_off[p],
+// phase_off[p+1]), each range padded with -1 to a multiple of TILE.
+struct Lists {
+  int* state;
+  int* iters;
+  int* status;
+  int* slot_col;    // N_pad + NPHASE*TILE entries
+  int* phase_off;   // NPHASE + 1 entries
+  int* n_total;     // number of unfinished instances (read by the host)
+};
+
+struct DalmInit {
+  int n, n_pad, lds, e0;
+  const float* V;
+  const float* W;
+  const float* beta;
+  const float* eps;
+  float* zscale;
+  float* U;
+};
+
+struct DalmCheck {
+  int N;
+  const float* partial;
+  int ldp, ntiles;
+  float tol;            // < 0: never converge (fixed iteration count)
+  float floor[NPHASE];  // the final test uses max(tol, floor[phase])
+  float sw;             // exit threshold of a non-final phase
+  int final_phase;
+  Lists L;
+  const float* eps;     // P_{1,2} only (with zscale)
+  const float* beta;
+  float* zscale;
+  long long* stat;      // [p] launches with work in phase p, [3 + p] summed active columns
+};
+
+struct P12Fix {
+  int n, e0, lds;
+  const int* slot_col;
+  const int* phase_off;
+  const float* V;
+  const float* W;
+  const float* beta;
+  const float* zscale;
+  float* U;
+};
+
+void penalties(hipStream_t s, int N, int m, const float* b, int ldb, float fixed, int mode,
+               float* pen, float* ipen);
+void dalm_init_u(hipStream_t s, int N, const DalmInit& a);
+void init_lists(hipStream_t s, int N, int phase0, const Lists& L, long long* stat);
+void dalm_check(hipStream_t s, const DalmCheck& a);
+void p12_fix(hipStream_t s, int n_blocks, const P12Fix& a);
+void copy_block(hipStream_t s, int rows, int N, const float* src, int lds, int r0, float* dst,
+                int ldd);
+void copy_in(hipStream_t s, int rows, int N, const float* src, int lds, float* dst, int ldd,
+             int r0);
+void finish_status(hipStream_t s, int N, int fixed, const int* iters, const int* status,
+                   int* it_out, int* st_out);
+
+}  // namespace l1

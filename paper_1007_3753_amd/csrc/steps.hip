@@ -1,0 +1,270 @@
+// Small per-solve and per-iteration kernels: penalty per instance, initial
+// z/u, the convergence test with active-list compaction, the P_{1,2} block
+// prox fix-up, PALM's outer-step elementwise work, and output extraction.
+#include "steps.h"
+
+namespace l1 {
+
+__device__ float wg_sum(float v, float* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  const float r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---- penalties ------------------------------------------------------------
+// mode 0 (DALM): pen = beta > 0 ? beta : ||b||_1/m (1 when b = 0)
+// mode 1 (PALM): pen = xi > 0 ? xi : 2m/||b||_1     (1 when b = 0)
+__global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int ldb,
+                                                      float fixed, int mode, float* pen,
+                                                      float* ipen) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x;
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < m; i += 256) s += fabsf(b[(long)c * ldb + i]);
+  s = wg_sum(s, sh);
+  if (threadIdx.x == 0) {
+    float p;
+    if (fixed > 0.0f) p = fixed;
+    else if (mode == 0) p = (s > 0.0f) ? s / (float)m : 1.0f;
+    else p = (s > 0.0f) ? 2.0f * (float)m / s : 1.0f;
+    pen[c] = p;
+    ipen[c] = 1.0f / p;
+  }
+}
+void penalties(hipStream_t s, int N, int m, const float* b, int ldb, float fixed, int mode,
+               float* pen, float* ipen) {
+  if (N <= 0) return;
+  penalty_kernel<<<N, 256, 0, s>>>(m, b, ldb, fixed, mode, pen, ipen);
+  L1_HIP(hipGetLastError());
+}
+
+// ---- DALM initial operand: u = z_1 - w_0/beta, z_1 = prox(v_0 + w_0/beta) ----
+__global__ __launch_bounds__(256) void dalm_init_u_kernel(DalmInit a) {
+  __shared__ float sh[256];
+  const int c = blockIdx.x;
+  const float bt = a.beta[c], ib = 1.0f / bt;
+  const float* V = a.V + (long)c * a.lds;
+  const float* W = a.W + (long)c * a.lds;
+  float zs = 1.0f;
+  if (a.e0 < a.n) {
+    float se = 0.0f;
+    for (int i = a.e0 + threadIdx.x; i < a.n; i += 256) {
+      const float s = V[i] + W[i] * ib;
+      se += s * s;
+    }
+    se = wg_sum(se, sh);
+    const float tau = a.eps[c] * ib;
+    zs = (se > 0.0f) ? fmaxf(0.0f, 1.0f - tau / sqrtf(se)) : 0.0f;
+    if (threadIdx.x == 0) a.zscale[c] = zs;
+  }
+  for (int i = threadIdx.x; i < a.n_pad; i += 256) {
+    const float s = V[i] + W[i] * ib;
+    const float z = (i >= a.e0) ? s * zs : fminf(fmaxf(s, -1.0f), 1.0f);
+    a.U[(long)c * a.lds + i] = z - W[i] * ib;
+  }
+}
+void dalm_init_u(hipStream_t s, int N, const DalmInit& a) {
+  if (N <= 0) return;
+  dalm_init_u_kernel<<<N, 256, 0, s>>>(a);
+  L1_HIP(hipGetLastError());
+}
+
+// ---- lists -------------------------------------------------------------------
+__global__ void init_lists_kernel(int N, int phase0, Lists L, long long* stat) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < N) {
+    L.state[c] = phase0;
+    L.iters[c] = 0;
+    L.status[c] = L1_MAXITER;
+  }
+  const int npad = (N + TILE - 1) / TILE * TILE;
+  if (c < npad) L.slot_col[c] = (c < N) ? c : -1;
+  if (c == 0) {
+    for (int p = 0; p <= NPHASE; ++p) L.phase_off[p] = (p <= phase0) ? 0 : npad;
+    *L.n_total = N;
+    for (int i = 0; i < 8; ++i) stat[i] = 0;
+  }
+}
+void init_lists(hipStream_t s, int N, int phase0, const Lists& L, long long* stat) {
+  const int npad = (N + TILE - 1) / TILE * TILE;
+  init_lists_kernel<<<(npad + 255) / 256, 256, 0, s>>>(N, phase0, L, stat);
+  L1_HIP(hipGetLastError());
+}
+
+// Block-wide stable compaction of per-thread flags (1024 threads = 16 waves).
+__device__ int compact_pos(bool flag, int* wave_tot, int* total_out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int before = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) wave_tot[wave] = __popcll(m);
+  __syncthreads();
+  int off = 0, total = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) off += wave_tot[w];
+    total += wave_tot[w];
+  }
+  __syncthreads();
+  *total_out = total;
+  return off + before;
+}
+
+// ---- DALM convergence test and compaction (one workgroup) -------------------
+__global__ __launch_bounds__(1024) void dalm_check_kernel(DalmCheck a) {
+  __shared__ int wt[16];
+  __shared__ int cnt[NPHASE], before[NPHASE];
+  if (threadIdx.x < NPHASE) {
+    cnt[threadIdx.x] = 0;
+    before[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  // pass 1: tests and state transitions
+  const float sw2 = a.sw * a.sw;
+  int mycnt[NPHASE] = {0, 0, 0}, mybefore[NPHASE] = {0, 0, 0};
+  for (int c = threadIdx.x; c < a.N; c += 1024) {
+    int st = a.L.state[c];
+    if (st >= NPHASE) continue;
+    mybefore[st] += 1;
+    float d2 = 0.f, w2 = 0.f, l1 = 0.f, gp = 0.f, se = 0.f;
+    for (int t = 0; t < a.ntiles; ++t) {
+      const float* p = a.partial + (long)t * NPART * a.ldp + c;
+      d2 += p[0];
+      w2 += p[a.ldp];
+      l1 += p[2 * (long)a.ldp];
+      gp += p[3 * (long)a.ldp];
+      se += p[4 * (long)a.ldp];
+    }
+    a.L.iters[c] += 1;
+    const float gap = fabsf(gp);  // sum of |w_i| (1 - sign(w_i) v_i) over the l1 rows
+    const bool finite = isfinite(d2) && isfinite(w2) && isfinite(gap);
+    if (!finite) {
+      st = NPHASE;
+      a.L.status[c] = L1_NONFINITE;
+    } else if (st != a.final_phase) {
+      if (d2 <= sw2 * w2 && gap <= a.sw * l1) ++st;
+    } else if (a.tol >= 0.0f) {
+      const float t = fmaxf(a.tol, a.floor[st]);
+      if (d2 <= t * t * w2 && gap <= t * l1) {
+        st = NPHASE;
+        a.L.status[c] = L1_CONVERGED;
+      }
+    }
+    if (a.zscale && st < NPHASE) {
+      const float tau = a.eps[c] / a.beta[c];
+      a.zscale[c] = (se > 0.0f) ? fmaxf(0.0f, 1.0f - tau / sqrtf(se)) : 0.0f;
+    }
+    a.L.state[c] = st;
+    if (st < NPHASE) mycnt[st] += 1;
+  }
+  for (int p = 0; p < NPHASE; ++p) {
+    if (mycnt[p]) atomicAdd(&cnt[p], mycnt[p]);
+    if (mybefore[p]) atomicAdd(&before[p], mybefore[p]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && a.stat) {
+    for (int p = 0; p < NPHASE; ++p)
+      if (before[p] > 0) {
+        a.stat[p] += 1;
+        a.stat[3 + p] += before[p];
+      }
+    if (before[0] + before[1] + before[2] > 0) a.stat[6] += 1;
+  }
+  int off[NPHASE + 1];
+  off[0] = 0;
+  for (int p = 0; p < NPHASE; ++p) off[p + 1] = off[p] + (cnt[p] + TILE - 1) / TILE * TILE;
+  // pass 2: stable compaction into the phase segments
+  int base[NPHASE] = {0, 0, 0};
+  for (int c0 = 0; c0 < a.N; c0 += 1024) {
+    const int c = c0 + threadIdx.x;
+    const int st = (c < a.N) ? a.L.state[c] : NPHASE;
+    for (int p = 0; p < NPHASE; ++p) {
+      int tot;
+      const int pos = compact_pos(st == p, wt, &tot);
+      if (st == p) a.L.slot_col[off[p] + base[p] + pos] = c;
+      base[p] += tot;
+    }
+  }
+  // idle padding slots
+  for (int p = 0; p < NPHASE; ++p)
+    for (int s = off[p] + cnt[p] + threadIdx.x; s < off[p + 1]; s += 1024) a.L.slot_col[s] = -1;
+  if (threadIdx.x == 0) {
+    for (int p = 0; p <= NPHASE; ++p) a.L.phase_off[p] = off[p];
+    *a.L.n_total = cnt[0] + cnt[1] + cnt[2];
+  }
+}
+void dalm_check(hipStream_t s, const DalmCheck& a) {
+  dalm_check_kernel<<<1, 1024, 0, s>>>(a);
+  L1_HIP(hipGetLastError());
+}
+
+// ---- P_{1,2}: next operand on the eps-ball rows once the column norm is known --
+__global__ __launch_bounds__(256) void p12_fix_kernel(P12Fix a) {
+  const int slot = blockIdx.x;
+  if (slot >= a.phase_off[NPHASE]) return;
+  const int c = a.slot_col[slot];
+  if (c < 0) return;
+  const float ib = 1.0f / a.beta[c];
+  const float zs = a.zscale[c];
+  for (int i = a.e0 + threadIdx.x; i < a.n; i += 256) {
+    const long idx = (long)c * a.lds + i;
+    const float w = a.W[idx];
+    const float s2 = a.V[idx] + w * ib;
+    a.U[idx] = s2 * zs - w * ib;
+  }
+}
+void p12_fix(hipStream_t s, int n_blocks, const P12Fix& a) {
+  if (n_blocks <= 0) return;
+  p12_fix_kernel<<<n_blocks, 256, 0, s>>>(a);
+  L1_HIP(hipGetLastError());
+}
+
+// ---- outputs -------------------------------------------------------------------
+__global__ void copy_block_kernel(int rows, int N, const float* src, int lds, int r0, float* dst,
+                                  int ldd) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * N) return;
+  const int i = (int)(e % rows), c = (int)(e / rows);
+  dst[(long)c * ldd + i] = src[(long)c * lds + r0 + i];
+}
+void copy_block(hipStream_t s, int rows, int N, const float* src, int lds, int r0, float* dst,
+                int ldd) {
+  const long n = (long)rows * N;
+  if (n <= 0 || !dst) return;
+  copy_block_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rows, N, src, lds, r0, dst, ldd);
+  L1_HIP(hipGetLastError());
+}
+__global__ void copy_in_kernel(int rows, int N, const float* src, int lds, float* dst, int ldd,
+                               int r0) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * N) return;
+  const int i = (int)(e % rows), c = (int)(e / rows);
+  dst[(long)c * ldd + r0 + i] = src[(long)c * lds + i];
+}
+void copy_in(hipStream_t s, int rows, int N, const float* src, int lds, float* dst, int ldd,
+             int r0) {
+  const long n = (long)rows * N;
+  if (n <= 0) return;
+  copy_in_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rows, N, src, lds, dst, ldd, r0);
+  L1_HIP(hipGetLastError());
+}
+__global__ void finish_status_kernel(int N, int fixed, const int* iters, const int* status,
+                                     int* it_out, int* st_out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  if (it_out) it_out[c] = (fixed > 0) ? fixed : iters[c];
+  if (st_out) st_out[c] = (fixed > 0) ? (status[c] == L1_NONFINITE ? L1_NONFINITE : L1_CONVERGED)
+                                      : status[c];
+}
+void finish_status(hipStream_t s, int N, int fixed, const int* iters, const int* status,
+                   int* it_out, int* st_out) {
+  if (N <= 0 || (!it_out && !st_out)) return;
+  finish_status_kernel<<<(N + 255) / 256, 256, 0, s>>>(N, fixed, iters, status, it_out, st_out);
+  L1_HIP(hipGetLastError());
+}
+
+}  // namespace l1

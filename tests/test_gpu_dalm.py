@@ -1,0 +1,176 @@
+"""GPU parity of the DALM path (C ABI via the Python binding) against the FP64
+oracle, on seeded synthetic inputs.
+
+Iterate-level parity: after exactly k iterations the GPU state equals the
+oracle's Algorithm-2 iterate to FP32 accuracy.  Converged parity: the GPU
+result matches the exact LP optimum (HiGHS on the split LP) to the bound the
+precision mode promises (FP32 1e-4, split-BF16 1e-4, BF16 + refinement 1e-3).
+"""
+import numpy as np
+import pytest
+
+from oracle import dalm as oracle_dalm, p1_lp, full_matrix, kkt_report, qp_fista
+from workloads import tiny_dense, dense_p1, cab_problem, dense_qp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _plan(A, **kw):
+    from paper_1007_3753_amd import Plan
+    return Plan(torch.as_tensor(A, device="cuda"), **kw)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_library_loads_on_gpu():
+    import paper_1007_3753_amd as pkg
+    lib = pkg.load()
+    assert lib is not None and torch.cuda.is_available()
+
+
+@pytest.mark.parametrize("k", [1, 3, 40])
+def test_dense_fixed_iterations_match_oracle(k):
+    P = tiny_dense(20, 60, N=3, key=11)
+    pl = _plan(P.A, max_batch=3)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
+    o = oracle_dalm(P.A, P.b, fixed_iters=k)
+    assert _rel(_np(r.x), o.w) < 2e-5
+    assert _rel(_np(r.y), o.y) < 2e-5
+    assert np.all(_np(r.iters) == k) and np.all(_np(r.status) == 0)
+
+
+@pytest.mark.parametrize("k", [1, 5, 60])
+def test_cab_fixed_iterations_match_oracle(k):
+    # 130 rows / 49 columns: several tiles with ragged edges in both dimensions
+    P = cab_problem(m=130, classes=7, per_class=7, N=70, cfg=201)
+    pl = _plan(P.A, structure="cab", max_batch=70)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
+    o = oracle_dalm(P.A, P.b[:, :6], structure="cab", fixed_iters=k)
+    w = np.vstack([_np(r.x), _np(r.e)])[:, :6]
+    assert _rel(w, o.w) < 5e-5
+    assert _rel(_np(r.y)[:, :6], o.y) < 5e-5
+
+
+def test_dense_p1_converged_matches_lp_and_planted():
+    P = dense_p1(trial=3)
+    pl = _plan(P.A, max_batch=1)
+    b = torch.as_tensor(P.b, device="cuda")
+    r = pl.solve(b, tol=1e-6, max_iter=20000)
+    x_lp, _ = p1_lp(P.A, P.b[:, 0])
+    assert int(r.status[0]) == 0
+    assert _rel(_np(r.x)[:, 0], x_lp) < 1e-4
+    assert _rel(_np(r.x)[:, 0], P.x0[:, 0].astype(float)) < 1e-4
+    rep = pl.kkt(b, r.x, y=r.y).cpu().numpy()[0]
+    ref = kkt_report(P.A, P.b[:, 0], _np(r.x)[:, 0], _np(r.y)[:, 0])
+    np.testing.assert_allclose(rep, [ref["primal"], ref["dual_inf"], ref["sign"], ref["gap"]],
+                               rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision,bound", [("fp32", 1e-4), ("bf16x3", 1e-4), ("bf16_refine", 1e-3)])
+def test_cab_converged_matches_lp(precision, bound):
+    P = cab_problem(m=300, classes=20, per_class=7, N=96, frac=0.3, cfg=202)
+    pl = _plan(P.A, structure="cab", precision=precision, max_batch=96)
+    b = torch.as_tensor(P.b, device="cuda")
+    r = pl.solve(b, tol=5e-6, max_iter=30000)
+    st = _np(r.status)
+    assert np.all(st == 0), np.unique(st, return_counts=True)
+    Af = full_matrix(P.A, "cab")
+    for j in (0, 37, 95):
+        w_lp, _ = p1_lp(Af, P.b[:, j])
+        x = _np(r.x)[:, j]
+        assert _rel(x, w_lp[:P.n_dict]) < bound, (j, _rel(x, w_lp[:P.n_dict]))
+    rep = pl.kkt(b, r.x, e=r.e, y=r.y).cpu().numpy()
+    assert rep[:, 0].max() < 1e-5 and rep[:, 3].max() < 1e-4
+
+
+def test_batched_equals_single_instance():
+    P = cab_problem(m=130, classes=7, per_class=7, N=20, cfg=203)
+    pl = _plan(P.A, structure="cab", max_batch=20)
+    b = torch.as_tensor(P.b, device="cuda")
+    rb = pl.solve(b, tol=1e-6, max_iter=20000)
+    for j in (0, 7, 19):
+        r1 = pl.solve(b[:, j:j + 1], tol=1e-6, max_iter=20000)
+        # same per-column arithmetic in the same order: bitwise equal
+        assert torch.equal(r1.x[:, 0], rb.x[:, j])
+        assert int(r1.iters[0]) == int(rb.iters[j])
+
+
+def test_zero_rhs_and_mixed_batch():
+    P = cab_problem(m=130, classes=7, per_class=7, N=5, cfg=204)
+    b = P.b.copy()
+    b[:, 2] = 0.0
+    pl = _plan(P.A, structure="cab", max_batch=8)
+    r = pl.solve(torch.as_tensor(b, device="cuda"), tol=1e-6, max_iter=20000)
+    assert int(r.status[2]) == 0 and int(r.iters[2]) == 1
+    assert float(r.x[:, 2].abs().max()) == 0.0 and float(r.e[:, 2].abs().max()) == 0.0
+    assert np.all(_np(r.status) == 0)
+
+
+def test_nonfinite_input_reported_per_instance():
+    P = cab_problem(m=130, classes=7, per_class=7, N=3, cfg=205)
+    b = P.b.copy()
+    b[5, 1] = np.nan
+    pl = _plan(P.A, structure="cab", max_batch=3)
+    r = pl.solve(torch.as_tensor(b, device="cuda"), tol=1e-6, max_iter=30000)
+    st = _np(r.status)
+    assert st[1] == 2 and st[0] == 0 and st[2] == 0
+
+
+def test_maxiter_status():
+    P = cab_problem(m=130, classes=7, per_class=7, N=2, cfg=206)
+    pl = _plan(P.A, structure="cab", max_batch=2)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), tol=1e-9, max_iter=3)
+    assert np.all(_np(r.status) == 1) and np.all(_np(r.iters) == 3)
+
+
+def test_error_paths():
+    from paper_1007_3753_amd import L1Error
+    P = tiny_dense(10, 30, key=12)
+    pl = _plan(P.A, max_batch=2)
+    with pytest.raises(L1Error) as ei:
+        pl.solve(torch.zeros(10, 3, device="cuda"))
+    assert ei.value.code == -1
+    A = P.A.copy()
+    A[3] = A[2]  # dependent rows: A A^T singular
+    with pytest.raises(L1Error) as ei:
+        _plan(A, max_batch=1)
+    assert ei.value.code == -2
+    with pytest.raises(L1Error) as ei:
+        _plan(P.A, problem="qp", lam=0.1, max_batch=1)   # DALM-QP needs beta
+    assert ei.value.code == -1
+
+
+def test_qp_dalm_matches_fista():
+    P = tiny_dense(40, 120, N=4, key=13)
+    lam = 0.05
+    beta = float(np.mean(np.abs(P.b).sum(axis=0) / 40))
+    pl = _plan(P.A, problem="qp", lam=lam, beta=beta, max_batch=4)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), tol=1e-7, max_iter=50000)
+    assert np.all(_np(r.status) == 0)
+    for j in range(4):
+        xf = qp_fista(P.A, P.b[:, j], lam, iters=40000)
+        assert _rel(_np(r.x)[:, j], xf) < 1e-4
+
+
+def test_p12_dalm_matches_oracle():
+    P = tiny_dense(40, 120, N=3, key=14)
+    A, b = P.A.astype(float), P.b.astype(float)
+    eps = np.array([0.3, 0.5, 0.8]) * np.linalg.norm(b, axis=0)
+    o = oracle_dalm(A, b, problem="p12", eps=eps, tol=1e-10, max_iter=200000)
+    pl = _plan(P.A, problem="p12", max_batch=3)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), eps=torch.as_tensor(eps, dtype=torch.float32),
+                 tol=1e-6, max_iter=100000)
+    assert np.all(_np(r.status) == 0)
+    assert _rel(_np(r.x), o.w[:120]) < 1e-4
+    # fixed-iteration parity of the block prox
+    r5 = pl.solve(torch.as_tensor(P.b, device="cuda"), eps=torch.as_tensor(eps, dtype=torch.float32),
+                  max_iter=-7)
+    o5 = oracle_dalm(A, b, problem="p12", eps=eps, fixed_iters=7)
+    assert _rel(np.vstack([_np(r5.x), _np(r5.e)]), o5.w) < 5e-5
