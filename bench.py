@@ -136,15 +136,19 @@ def main():
     # ---- roofline of the iteration kernel (gemm_kernel<EPI_DALM>) -----------
     n_pad = (n_full + 63) // 64 * 64
     cols = {"fp32": agg["cols_fp32"], "bf16": agg["cols_bf16"], "split": agg["cols_split"]}
-    launches = {"fp32": agg["launch_fp32"], "bf16": agg["launch_bf16"], "split": agg["launch_split"]}
     flops = {k: 2.0 * n_full * n_full * c for k, c in cols.items()}
-    op_bytes = {"fp32": 4, "bf16": 2, "split": 4}
-    # operator read once per launch per arithmetic present + per instance: u read,
-    # (v, w, c) read, (v, w, u) written, FP32
-    bytes_total = sum(n_full * n_full * op_bytes[k] * launches[k] for k in launches) + \
-        28.0 * n_full * sum(cols.values())
     kern_s = agg["timed_ms"] / 1e3
     nl = max(agg["timed_launches"], 1.0)
+    # algorithmic bytes of one launch: the operator read once, in the element
+    # size of the arithmetic (weighted by the instances each arithmetic
+    # served), plus per instance the operand u read in that arithmetic
+    # (FP32 4 B, BF16 2 B, split 4 B), v, w, c read and v, w, u written (FP32)
+    # and the BF16 split of u written (4 B) when a BF16 mode runs
+    esize = {"fp32": 4, "bf16": 2, "split": 4}
+    tot_cols = max(sum(cols.values()), 1.0)
+    op_bytes = nl * n_full * n_full * sum(esize[k] * cols[k] for k in cols) / tot_cols
+    low = args.precision != "fp32"
+    bytes_total = op_bytes + n_full * sum(cols[k] * (esize[k] + 24 + (4 if low else 0)) for k in cols)
     t_mfma = sum(flops[k] / (PEAK_TFLOPS[k] * 1e12) for k in flops)
     t_hbm = bytes_total / (PEAK_HBM_GBS * 1e9)
     tot_flops = sum(flops.values())

@@ -158,9 +158,10 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
 
 /* Statistics of the last l1_alm_solve on this plan; writes min(n, 14)
  * doubles to out (host memory):
- *   [0..2]  launches of the per-iteration product that had work, by the
- *           arithmetic of their tiles: FP32, BF16, split BF16
- *   [3..5]  instances summed over those launches, by arithmetic
+ *   [0..2]  column tiles (64 instances) of the per-iteration product that
+ *           had work, summed over the launches, by the arithmetic of the
+ *           tile: FP32, BF16, split BF16
+ *   [3..5]  instances summed over those tiles and launches, by arithmetic
  *   [6]     total duration (ms) of the timed product launches that had work
  *           (desc.time_kernels = 1; HIP events around each launch), else 0
  *   [7]     number of such timed launches

@@ -244,6 +244,12 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   for (int b = 0; b < 2; ++b) {
     p->Uf[b] = dalloc<float>(st, o);
     L1_HIP(hipMemsetAsync(p->Uf[b], 0, sizeof(float) * st, s));
+    if (low) {
+      p->Uh[b] = dalloc<uint16_t>(st, o);
+      p->Ul[b] = dalloc<uint16_t>(st, o);
+      L1_HIP(hipMemsetAsync(p->Uh[b], 0, sizeof(uint16_t) * st, s));
+      L1_HIP(hipMemsetAsync(p->Ul[b], 0, sizeof(uint16_t) * st, s));
+    }
   }
   p->bb = dalloc<float>((size_t)p->m_pad * Np, o);
   p->aux = dalloc<float>((size_t)p->m_pad * Np * 4, o);
@@ -253,8 +259,14 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   p->tscal = dalloc<float>(Np * 4, o);
   const int ntiles = rows / TILE;
   p->ntiles = ntiles;
-  p->partial = dalloc<float>((size_t)ntiles * NPART * Np, o);
-  p->ints = dalloc<int>(Np * 8 + 256, o);
+  p->partial = dalloc<float>((size_t)2 * ntiles * NPART * Np, o);  // two buffers
+  // split-K workspace and policy (L1ALM_KSPLIT_TARGET: workgroups aimed for;
+  // L1ALM_KSPLIT_MAX: largest split)
+  p->ws_tiles = 48;
+  p->ws = dalloc<float>((size_t)p->ws_tiles * TILE * rows, o);
+  if (const char* e = std::getenv("L1ALM_KSPLIT_TARGET")) p->ks_target = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("L1ALM_KSPLIT_MAX")) p->ks_max = std::max(1, std::min(8, std::atoi(e)));
+  p->ints = dalloc<int>(Np * 8 + 512, o);
   p->stat = dalloc<long long>(8, o);
   p->kkt_rbuf = dalloc<double>((size_t)m * Np, o);
   L1_HIP(hipHostMalloc((void**)&p->h_total, sizeof(int) * 4, 0));

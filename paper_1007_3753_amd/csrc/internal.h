@@ -75,7 +75,7 @@ void kkt64(hipStream_t s, int problem, int m, int nd, int split, const float* A,
 // ---- iteration kernels ---------------------------------------------------
 // Arithmetic of a product.  Phase p of an instance selects PHASE_PREC[p].
 enum Prec { PREC_BF16 = 0, PREC_BF16X3 = 1, PREC_F32 = 2 };
-enum Epi { EPI_STORE = 0, EPI_DALM = 1, EPI_FISTA = 2 };
+enum Epi { EPI_STORE = 0, EPI_DALM = 1, EPI_FISTA = 2, EPI_PARTIAL = 3 };
 constexpr int NPHASE = 3;   // phase index == Prec
 
 struct GemmArgs {
@@ -86,8 +86,11 @@ struct GemmArgs {
   const uint16_t* Ahi;
   const uint16_t* Alo;
   int lda;
-  // B-operand: K x ncols FP32, element (k, col) at B[col*ldb + k].
+  // B-operand: K x ncols, element (k, col) at B[col*ldb + k]: FP32 (B) and,
+  // for BF16 tiles, its BF16 hi / lo split (Bhi, Blo).
   const float* B;
+  const uint16_t* Bhi;
+  const uint16_t* Blo;
   int ldb;
   int M;   // padded rows (multiple of TILE)
   int K;   // padded reduction length (multiple of KPAD)
@@ -110,7 +113,9 @@ struct GemmArgs {
   float* W;             // DALM: w = [x; e]             | FISTA: w (last shrink output)
   const float* C;       // DALM: c = A^T G^{-1} b/beta  | FISTA: h = A^T (b - e + theta/xi)
   const float* beta;    // DALM: beta per column        | FISTA: xi per column
-  float* U;             // DALM: next B-operand u (FP32)
+  float* U;             // DALM: next B-operand u (FP32) ...
+  uint16_t* Uhi;        // ... and its BF16 hi / lo split (may be null when
+  uint16_t* Ulo;        //     no BF16 phase runs)
   float* partial;       // partial[(tile*NPART + q)*ldp + col]
   int ldp;
   int n_l1;             // DALM: rows < n_l1 carry the l1 norm (gap sums)
@@ -118,12 +123,36 @@ struct GemmArgs {
   const float* zscale;  // DALM P_{1,2}: block-prox scale of the previous z-step per column
   float inv_L;          // FISTA: 1/L
   float gamma;          // FISTA: (t_l - 1)/t_{l+1}
+  // ---- split-K: EPI_PARTIAL launches split the K range in ksplit parts and
+  // write raw products ws[(s*ws_slots + slot)*M + row]; the following
+  // EPI_DALM / EPI_FISTA launch with the same ws sums the parts in order
+  // s = 0..ksplit-1 instead of running a main loop.
+  int ksplit;           // >= 1
+  float* ws;            // null: no split-K
+  int ws_slots;         // slot stride of ws (= n_col_tiles * TILE of the launch)
+  int n_ctiles;         // column tiles covered by the launch grid
+  // ---- per-instance state (DALM iteration launches; null otherwise).  The
+  // prologue of a launch tests the previous iteration of its 64 columns from
+  // prev_partial, skips finished columns and runs the tile in the highest
+  // phase among its live columns; row tile 0 records the new state.
+  const int* state_in;   // phases before this launch (read by every workgroup)
+  int* state_out;        // phases after its test (written by row tile 0)
+  int* iters;
+  int* status;
+  const float* prev_partial;   // null: no test (first iteration of a solve)
+  float tp_tol, tp_sw, tp_floor[3];
+  int tp_final;
+  const float* eps;            // P_{1,2} radii (the ball scale comes from prev_partial)
+  long long* stat;             // [3 + prec] += live columns, [prec] += column tiles
 };
 
 // Number of column tiles a launch must cover for up to n columns split over
 // the phases (each phase range is padded to a multiple of TILE).
 inline int col_tiles_for(int n) { return (n + TILE - 1) / TILE + NPHASE - 1; }
 void launch_gemm(hipStream_t s, int epi, const GemmArgs& a, int n_col_tiles);
+// One iteration product with epilogue `epi`, split over ksplit K ranges when
+// ksplit > 1 (two launches, workspace a.ws), else fused in one launch.
+void launch_product(hipStream_t s, int epi, GemmArgs a, int n_col_tiles, int ksplit);
 
 // ---- small per-iteration kernels ---------------------------------------
 void fill_iota(hipStream_t s, int* p, int n);

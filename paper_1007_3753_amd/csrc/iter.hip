@@ -20,6 +20,7 @@
 // register prefetch of the next slice.  Both operands are K-contiguous, so
 // every lane moves 16-byte vectors.
 #include "internal.h"
+#include "dalm_test.h"
 
 namespace l1 {
 
@@ -51,150 +52,189 @@ __device__ inline void st16(void* p, u4 v) { *reinterpret_cast<u4*>(p) = v; }
 // LDS tiles: 0 = A (hi), 1 = B (hi), 2 = A lo, 3 = B lo; rows of LDSROW bytes
 constexpr int LDSTILE = 64 * LDSROW;
 
+// The K loop of a workgroup is a chain of global-memory round trips; each
+// takes ~1 us under load, far longer than the MFMA work on one slice.  Both
+// main loops keep D slices in flight in registers: slice k + D is requested
+// as soon as slice k has been moved to LDS.  Every load is unconditional (the
+// slice index is clamped, idle columns read column 0 and are masked to zero)
+// and the steady-state loop runs a multiple of D steps, so the wait inserted
+// before a register set is consumed always leaves the younger D - 1 slices in
+// flight, also across the loop back-edge.  D is a compile-time constant so
+// every register set is statically indexed.
+
 // ---- FP32 main loop: 32-element K slices, v_mfma_f32_16x16x4_f32 ----------
+template <int D>
 __device__ inline void mainloop_f32(const GemmArgs& a, int i0, const int* colidx,
-                                    unsigned char* lds, f4 (&acc)[2][2]) {
+                                    unsigned char* lds, f4 (&acc)[2][2], int kb, int ke) {
   const int tid = threadIdx.x;
   const int ch = tid & 7, rr = tid >> 3;
   const char* A = reinterpret_cast<const char*>(a.A32);
   const char* B = reinterpret_cast<const char*>(a.B);
   const long arow0 = (long)(i0 + rr) * a.lda * 4, arow1 = (long)(i0 + rr + 32) * a.lda * 4;
   const int bc0 = colidx[rr], bc1 = colidx[rr + 32];
-  const long brow0 = (long)(bc0 < 0 ? 0 : bc0) * a.ldb * 4;
-  const long brow1 = (long)(bc1 < 0 ? 0 : bc1) * a.ldb * 4;
+  const bool v0 = bc0 >= 0, v1 = bc1 >= 0;
+  const long brow0 = (long)(v0 ? bc0 : 0) * a.ldb * 4;
+  const long brow1 = (long)(v1 ? bc1 : 0) * a.ldb * 4;
   const u4 z4 = {0u, 0u, 0u, 0u};
-  u4 ra0, ra1, rb0, rb1;
-  auto fetch = [&](long kb) {
-    const long off = kb + ch * 16;
-    ra0 = ld16(A + arow0 + off);
-    ra1 = ld16(A + arow1 + off);
-    rb0 = bc0 >= 0 ? ld16(B + brow0 + off) : z4;
-    rb1 = bc1 >= 0 ? ld16(B + brow1 + off) : z4;
-  };
+  // [kb, ke) is given in 64-element units; FP32 slices hold 32 elements
+  A += (long)kb * 256;
+  B += (long)kb * 256;
+  const int nk = 2 * (ke - kb);
+  if (nk <= 0) return;
+  u4 ra[D][2], rb[D][2];
+#define L1_FETCH_F32(d, kt)                                   \
+  {                                                           \
+    const long off = (long)min((kt), nk - 1) * 128 + ch * 16; \
+    ra[d][0] = ld16(A + arow0 + off);                         \
+    ra[d][1] = ld16(A + arow1 + off);                         \
+    const u4 b0 = ld16(B + brow0 + off);                      \
+    const u4 b1 = ld16(B + brow1 + off);                      \
+    rb[d][0] = v0 ? b0 : z4;                                  \
+    rb[d][1] = v1 ? b1 : z4;                                  \
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
-  const int nk = a.K / 32;
-  fetch(0);
-  for (int kt = 0; kt < nk; ++kt) {
-    st16(&lds[rr * LDSROW + ch * 16], ra0);
-    st16(&lds[(rr + 32) * LDSROW + ch * 16], ra1);
-    st16(&lds[LDSTILE + rr * LDSROW + ch * 16], rb0);
-    st16(&lds[LDSTILE + (rr + 32) * LDSROW + ch * 16], rb1);
-    __syncthreads();
-    if (kt + 1 < nk) fetch((long)(kt + 1) * 128);
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-      const int boff = kc * 64 + q * 16;
-      u4 fa[2], fb[2];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) fa[bi] = ld16(&lds[(wm * 32 + bi * 16 + li) * LDSROW + boff]);
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        fb[bj] = ld16(&lds[LDSTILE + (wn * 32 + bj * 16 + li) * LDSROW + boff]);
-      // lane (li, q) holds k = 4q..4q+3 of this 16-wide chunk; MFMA step s
-      // takes element s from every lane, so the four steps cover the chunk
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-            acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                __uint_as_float(fa[bi][s]), __uint_as_float(fb[bj][s]), acc[bi][bj], 0, 0, 0);
-    }
-    __syncthreads();
+#define L1_STEP_F32(d, kt_next)                                                              \
+  {                                                                                          \
+    st16(&lds[rr * LDSROW + ch * 16], ra[d][0]);                                             \
+    st16(&lds[(rr + 32) * LDSROW + ch * 16], ra[d][1]);                                      \
+    st16(&lds[LDSTILE + rr * LDSROW + ch * 16], rb[d][0]);                                   \
+    st16(&lds[LDSTILE + (rr + 32) * LDSROW + ch * 16], rb[d][1]);                            \
+    __syncthreads();                                                                         \
+    L1_FETCH_F32(d, kt_next)                                                                 \
+    _Pragma("unroll") for (int kc = 0; kc < 2; ++kc) {                                       \
+      const int boff = kc * 64 + q * 16;                                                     \
+      u4 fa[2], fb[2];                                                                       \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                        \
+        fa[i] = ld16(&lds[(wm * 32 + i * 16 + li) * LDSROW + boff]);                         \
+        fb[i] = ld16(&lds[LDSTILE + (wn * 32 + i * 16 + li) * LDSROW + boff]);               \
+      }                                                                                      \
+      /* lane (li, q) holds k = 4q..4q+3 of this 16-wide chunk; MFMA step s takes  */        \
+      /* element s from every lane, so the four steps cover the chunk             */        \
+      _Pragma("unroll") for (int s = 0; s < 4; ++s)                                          \
+      _Pragma("unroll") for (int bi = 0; bi < 2; ++bi)                                       \
+      _Pragma("unroll") for (int bj = 0; bj < 2; ++bj)                                       \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(                                  \
+            __uint_as_float(fa[bi][s]), __uint_as_float(fb[bj][s]), acc[bi][bj], 0, 0, 0);   \
+    }                                                                                        \
+    __syncthreads();                                                                         \
   }
+#pragma unroll
+  for (int d = 0; d < D; ++d) L1_FETCH_F32(d, d)
+  const int nmain = nk - nk % D;
+  for (int k0 = 0; k0 < nmain; k0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) L1_STEP_F32(d, k0 + d + D)
+  }
+  // remainder: slices nmain + d already sit in register set d
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (nmain + d < nk) L1_STEP_F32(d, nk - 1)
+#undef L1_STEP_F32
+#undef L1_FETCH_F32
 }
 
 // ---- BF16 main loops: 64-element K slices, v_mfma_f32_16x16x32_bf16 -------
-// The FP32 B-operand is split into BF16 hi (+ lo) while it is staged to LDS.
-template <bool SPLIT>
+// Both operands arrive already split into BF16 hi (+ lo): the operator once
+// per plan, the iterate by the previous iteration's epilogue.
+template <bool SPLIT, int D>
 __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colidx,
-                                     unsigned char* lds, f4 (&acc)[2][2]) {
+                                     unsigned char* lds, f4 (&acc)[2][2], int kb, int ke) {
   const int tid = threadIdx.x;
-  const int ch = tid & 7, rr = tid >> 3;    // A: 16-byte chunk, rows rr, rr + 32
-  const int bq = tid & 3, bcs = tid >> 2;   // B: quarter of the 256-byte FP32 slice, column slot
+  const int ch = tid & 7, rr = tid >> 3;    // 16-byte chunk, rows rr and rr + 32
   const char* Ah = reinterpret_cast<const char*>(a.Ahi);
   const char* Al = reinterpret_cast<const char*>(a.Alo);
-  const char* B = reinterpret_cast<const char*>(a.B);
+  const char* Bh = reinterpret_cast<const char*>(a.Bhi);
+  const char* Bl = reinterpret_cast<const char*>(a.Blo);
   const long arow0 = (long)(i0 + rr) * a.lda * 2, arow1 = (long)(i0 + rr + 32) * a.lda * 2;
-  const int bc = colidx[bcs];
-  const long brow = (long)(bc < 0 ? 0 : bc) * a.ldb * 4;
+  const int bc0 = colidx[rr], bc1 = colidx[rr + 32];
+  const bool v0 = bc0 >= 0, v1 = bc1 >= 0;
+  const long brow0 = (long)(v0 ? bc0 : 0) * a.ldb * 2;
+  const long brow1 = (long)(v1 ? bc1 : 0) * a.ldb * 2;
   const u4 z4 = {0u, 0u, 0u, 0u};
-  u4 rah0, rah1, ral0, ral1, rb[4];
-  auto fetch = [&](int kt) {
-    const long offa = (long)kt * 128 + ch * 16;
-    rah0 = ld16(Ah + arow0 + offa);
-    rah1 = ld16(Ah + arow1 + offa);
-    if (SPLIT) {
-      ral0 = ld16(Al + arow0 + offa);
-      ral1 = ld16(Al + arow1 + offa);
-    }
-    const long offb = (long)kt * 256 + bq * 64;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) rb[t] = bc >= 0 ? ld16(B + brow + offb + 16 * t) : z4;
-  };
-  auto stash = [&]() {
-    st16(&lds[rr * LDSROW + ch * 16], rah0);
-    st16(&lds[(rr + 32) * LDSROW + ch * 16], rah1);
-    if (SPLIT) {
-      st16(&lds[2 * LDSTILE + rr * LDSROW + ch * 16], ral0);
-      st16(&lds[2 * LDSTILE + (rr + 32) * LDSROW + ch * 16], ral1);
-    }
-    // 16 FP32 values -> 16 BF16 hi (+ 16 lo): two 16-byte vectors each
-    u4 h[2], l[2];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int e = 0; e < 4; e += 2) {
-        const float x0 = __uint_as_float(rb[t][e]), x1 = __uint_as_float(rb[t][e + 1]);
-        const uint32_t h0 = f2bf(x0), h1 = f2bf(x1);
-        h[t >> 1][(t & 1) * 2 + (e >> 1)] = h0 | (h1 << 16);
-        if (SPLIT) {
-          const uint32_t l0 = f2bf(x0 - bf2f((uint16_t)h0)), l1 = f2bf(x1 - bf2f((uint16_t)h1));
-          l[t >> 1][(t & 1) * 2 + (e >> 1)] = l0 | (l1 << 16);
-        }
-      }
-    st16(&lds[LDSTILE + bcs * LDSROW + bq * 32], h[0]);
-    st16(&lds[LDSTILE + bcs * LDSROW + bq * 32 + 16], h[1]);
-    if (SPLIT) {
-      st16(&lds[3 * LDSTILE + bcs * LDSROW + bq * 32], l[0]);
-      st16(&lds[3 * LDSTILE + bcs * LDSROW + bq * 32 + 16], l[1]);
-    }
-  };
+  Ah += (long)kb * 128;
+  Bh += (long)kb * 128;
+  if (SPLIT) {
+    Al += (long)kb * 128;
+    Bl += (long)kb * 128;
+  }
+  const int nk = ke - kb;
+  if (nk <= 0) return;
+  u4 rah[D][2], ral[D][2], rbh[D][2], rbl[D][2];
+#define L1_FETCH_BF(d, kt)                                    \
+  {                                                           \
+    const long off = (long)min((kt), nk - 1) * 128 + ch * 16; \
+    rah[d][0] = ld16(Ah + arow0 + off);                       \
+    rah[d][1] = ld16(Ah + arow1 + off);                       \
+    const u4 h0 = ld16(Bh + brow0 + off);                     \
+    const u4 h1 = ld16(Bh + brow1 + off);                     \
+    rbh[d][0] = v0 ? h0 : z4;                                 \
+    rbh[d][1] = v1 ? h1 : z4;                                 \
+    if (SPLIT) {                                              \
+      ral[d][0] = ld16(Al + arow0 + off);                     \
+      ral[d][1] = ld16(Al + arow1 + off);                     \
+      const u4 l0 = ld16(Bl + brow0 + off);                   \
+      const u4 l1 = ld16(Bl + brow1 + off);                   \
+      rbl[d][0] = v0 ? l0 : z4;                               \
+      rbl[d][1] = v1 ? l1 : z4;                               \
+    }                                                         \
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
-  const int nk = a.K / 64;
-  fetch(0);
-  for (int kt = 0; kt < nk; ++kt) {
-    stash();
-    __syncthreads();
-    if (kt + 1 < nk) fetch(kt + 1);
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc) {
-      const int boff = kc * 64 + q * 16;
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) {
-        const int ar = (wm * 32 + bi * 16 + li) * LDSROW + boff;
-        const bf8 ah = __builtin_bit_cast(bf8, ld16(&lds[ar]));
-        bf8 al;
-        if (SPLIT) al = __builtin_bit_cast(bf8, ld16(&lds[2 * LDSTILE + ar]));
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          const int br = LDSTILE + (wn * 32 + bj * 16 + li) * LDSROW + boff;
-          const bf8 bh = __builtin_bit_cast(bf8, ld16(&lds[br]));
-          if (SPLIT) {
-            const bf8 bl = __builtin_bit_cast(bf8, ld16(&lds[2 * LDSTILE + br]));
-            // small terms first: lo*hi + hi*lo, then hi*hi
-            acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi][bj], 0, 0, 0);
-            acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi][bj], 0, 0, 0);
-          }
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi][bj], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();
+#define L1_STEP_BF(d, kt_next)                                                                \
+  {                                                                                           \
+    st16(&lds[rr * LDSROW + ch * 16], rah[d][0]);                                             \
+    st16(&lds[(rr + 32) * LDSROW + ch * 16], rah[d][1]);                                      \
+    st16(&lds[LDSTILE + rr * LDSROW + ch * 16], rbh[d][0]);                                   \
+    st16(&lds[LDSTILE + (rr + 32) * LDSROW + ch * 16], rbh[d][1]);                            \
+    if (SPLIT) {                                                                              \
+      st16(&lds[2 * LDSTILE + rr * LDSROW + ch * 16], ral[d][0]);                             \
+      st16(&lds[2 * LDSTILE + (rr + 32) * LDSROW + ch * 16], ral[d][1]);                      \
+      st16(&lds[3 * LDSTILE + rr * LDSROW + ch * 16], rbl[d][0]);                             \
+      st16(&lds[3 * LDSTILE + (rr + 32) * LDSROW + ch * 16], rbl[d][1]);                      \
+    }                                                                                         \
+    __syncthreads();                                                                          \
+    L1_FETCH_BF(d, kt_next)                                                                   \
+    _Pragma("unroll") for (int kc = 0; kc < 2; ++kc) {                                        \
+      const int boff = kc * 64 + q * 16;                                                      \
+      bf8 ah[2], bh[2], al[2], bl[2];                                                         \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                         \
+        const int ar = (wm * 32 + i * 16 + li) * LDSROW + boff;                               \
+        const int br = LDSTILE + (wn * 32 + i * 16 + li) * LDSROW + boff;                     \
+        ah[i] = __builtin_bit_cast(bf8, ld16(&lds[ar]));                                      \
+        bh[i] = __builtin_bit_cast(bf8, ld16(&lds[br]));                                      \
+        if (SPLIT) {                                                                          \
+          al[i] = __builtin_bit_cast(bf8, ld16(&lds[2 * LDSTILE + ar]));                      \
+          bl[i] = __builtin_bit_cast(bf8, ld16(&lds[2 * LDSTILE + br]));                      \
+        }                                                                                     \
+      }                                                                                       \
+      /* four independent accumulators, issued round by round; small terms first */          \
+      if (SPLIT) {                                                                            \
+        _Pragma("unroll") for (int bi = 0; bi < 2; ++bi)                                      \
+        _Pragma("unroll") for (int bj = 0; bj < 2; ++bj)                                      \
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0); \
+        _Pragma("unroll") for (int bi = 0; bi < 2; ++bi)                                      \
+        _Pragma("unroll") for (int bj = 0; bj < 2; ++bj)                                      \
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0); \
+      }                                                                                       \
+      _Pragma("unroll") for (int bi = 0; bi < 2; ++bi)                                        \
+      _Pragma("unroll") for (int bj = 0; bj < 2; ++bj)                                        \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0); \
+    }                                                                                         \
+    __syncthreads();                                                                          \
   }
+#pragma unroll
+  for (int d = 0; d < D; ++d) L1_FETCH_BF(d, d)
+  const int nmain = nk - nk % D;
+  for (int k0 = 0; k0 < nmain; k0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) L1_STEP_BF(d, k0 + d + D)
+  }
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (nmain + d < nk) L1_STEP_BF(d, nk - 1)
+#undef L1_STEP_BF
+#undef L1_FETCH_BF
 }
 
 template <int EPI>
@@ -212,7 +252,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   const int RT = a.M / 64;
   const int r_lo = (xcd * RT) / 8, r_hi = ((xcd + 1) * RT) / 8, nr = r_hi - r_lo;
   if (nr <= 0) return;
-  const int rt = r_lo + j % nr, ct = j / nr;
+  const int ks = (EPI == EPI_PARTIAL) ? a.ksplit : 1;
+  const int rt = r_lo + j % nr, rest = j / nr;
+  const int ct = rest % a.n_ctiles, split = rest / a.n_ctiles;
+  if (split >= ks) return;
   const int i0 = rt * 64, slot0 = ct * 64;
   int nslots, prec;
   if (a.slot_col) {
@@ -224,20 +267,103 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   }
   if (slot0 >= nslots) return;  // uniform for the workgroup
   const int tid = threadIdx.x;
+  __shared__ float s_zsc[64];
+  __shared__ int s_prec, s_live;
   if (tid < 64) {
     const int sl = slot0 + tid;
     colidx[tid] = (sl < nslots) ? (a.slot_col ? a.slot_col[sl] : sl) : -1;
+    s_zsc[tid] = 1.0f;
+  }
+  if (tid == 0) {
+    s_prec = -1;
+    s_live = 0;
   }
   __syncthreads();
+  if (a.state_in) {
+    // convergence test of the previous iteration, 4 lanes per column
+    const int sl = tid >> 2, part = tid & 3;
+    const int col = colidx[sl];
+    const int st0 = (col >= 0) ? a.state_in[col] : NPHASE;
+    const bool live0 = st0 < NPHASE;
+    float sm[NPART];
+    column_sums(a.prev_partial, a.ldp, RT, col, live0 && a.prev_partial, part, sm);
+    int st = st0, stat_new = L1_MAXITER;
+    float zs = 1.0f;
+    if (live0 && a.prev_partial) {
+      TestParams tp;
+      tp.tol = a.tp_tol;
+      tp.sw = a.tp_sw;
+      tp.final_phase = a.tp_final;
+#pragma unroll
+      for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.tp_floor[q];
+      st = decide(tp, st0, sm, &stat_new);
+      if (a.eps) zs = ball_scale(sm[4], a.eps[col], a.beta[col]);
+    } else if (live0 && a.eps) {
+      zs = a.zscale[col];
+    }
+    if (part == 0 && col >= 0) {
+      if (st < NPHASE) {
+        s_zsc[sl] = zs;
+        atomicMax(&s_prec, st);
+        atomicAdd(&s_live, 1);
+      } else {
+        colidx[sl] = -1;
+      }
+      if (EPI != EPI_PARTIAL && rt == 0) {
+        a.state_out[col] = st;
+        if (live0) {
+          if (st >= NPHASE) a.status[col] = stat_new;
+          else a.iters[col] += 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_live == 0) return;  // every column of the tile has finished
+    prec = s_prec;
+    if (EPI != EPI_PARTIAL && rt == 0 && tid == 0 && a.stat) {
+      atomicAdd((unsigned long long*)&a.stat[3 + prec], (unsigned long long)s_live);
+      atomicAdd((unsigned long long*)&a.stat[prec], 1ull);
+    }
+  }
 
   f4 acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
-  if (prec == PREC_F32) mainloop_f32(a, i0, colidx, lds, acc);
-  else if (prec == PREC_BF16X3) mainloop_bf16<true>(a, i0, colidx, lds, acc);
-  else mainloop_bf16<false>(a, i0, colidx, lds, acc);
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
+    if (EPI != EPI_PARTIAL && a.ws) {
+      // split-K reduction: sum the parts in a fixed order
+      for (int sp = 0; sp < a.ksplit; ++sp)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            const long o = ((long)sp * a.ws_slots + slot0 + wn * 32 + bj * 16 + li) * a.M +
+                           i0 + wm * 32 + bi * 16 + 4 * q;
+            acc[bi][bj] += *reinterpret_cast<const f4*>(a.ws + o);
+          }
+    } else {
+      const int nk64 = a.K / 64;
+      const int kb = (split * nk64) / ks, ke = ((split + 1) * nk64) / ks;
+      if (prec == PREC_F32) mainloop_f32<8>(a, i0, colidx, lds, acc, kb, ke);
+      else if (prec == PREC_BF16X3) mainloop_bf16<true, 4>(a, i0, colidx, lds, acc, kb, ke);
+      else mainloop_bf16<false, 4>(a, i0, colidx, lds, acc, kb, ke);
+    }
+    if (EPI == EPI_PARTIAL) {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          const long o = ((long)split * a.ws_slots + slot0 + wn * 32 + bj * 16 + li) * a.M +
+                         i0 + wm * 32 + bi * 16 + 4 * q;
+          *reinterpret_cast<f4*>(a.ws + o) = acc[bi][bj];
+        }
+      return;
+    }
+  }
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
@@ -281,7 +407,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       if (EPI == EPI_DALM) {
         const float bt = a.beta[col];
         const float ib = 1.0f / bt;
-        const float zsc = a.zscale ? a.zscale[col] : 1.0f;
+        const float zsc = s_zsc[wn * 32 + bj * 16 + li];
         const f4 vo = *reinterpret_cast<const f4*>(a.V + idx);
         f4 vn4;
 #pragma unroll
@@ -311,6 +437,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         }
         *reinterpret_cast<f4*>(a.V + idx) = vn4;
         *reinterpret_cast<f4*>(a.U + idx) = un4;
+        if (a.Uhi) {
+          us4 h, l;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint16_t hb = f2bf(un4[r]);
+            h[r] = hb;
+            l[r] = f2bf(un4[r] - bf2f(hb));
+          }
+          *reinterpret_cast<us4*>(a.Uhi + idx) = h;
+          *reinterpret_cast<us4*>(a.Ulo + idx) = l;
+        }
       } else {  // EPI_FISTA
         const float xi = a.beta[col];
         const float thr = a.inv_L / xi;
@@ -358,15 +495,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   }
 }
 
-void launch_gemm(hipStream_t s, int epi, const GemmArgs& a, int n_col_tiles) {
-  if (n_col_tiles <= 0 || a.M <= 0) return;
+void launch_gemm(hipStream_t s, int epi, const GemmArgs& a0, int n_col_tiles) {
+  if (n_col_tiles <= 0 || a0.M <= 0) return;
+  GemmArgs a = a0;
+  a.n_ctiles = n_col_tiles;
+  if (a.ksplit < 1) a.ksplit = 1;
+  const int ks = (epi == EPI_PARTIAL) ? a.ksplit : 1;
   const int RT = a.M / 64;
   const int per_xcd = (RT + 7) / 8;
-  const unsigned grid = 8u * per_xcd * n_col_tiles;
+  const unsigned grid = 8u * per_xcd * n_col_tiles * ks;
   if (epi == EPI_STORE) gemm_kernel<EPI_STORE><<<grid, 256, 0, s>>>(a);
   else if (epi == EPI_DALM) gemm_kernel<EPI_DALM><<<grid, 256, 0, s>>>(a);
-  else gemm_kernel<EPI_FISTA><<<grid, 256, 0, s>>>(a);
+  else if (epi == EPI_FISTA) gemm_kernel<EPI_FISTA><<<grid, 256, 0, s>>>(a);
+  else gemm_kernel<EPI_PARTIAL><<<grid, 256, 0, s>>>(a);
   L1_HIP(hipGetLastError());
+}
+
+void launch_product(hipStream_t s, int epi, GemmArgs a, int n_col_tiles, int ksplit) {
+  if (ksplit > 1 && a.ws) {
+    a.ksplit = ksplit;
+    a.ws_slots = n_col_tiles * TILE;
+    launch_gemm(s, EPI_PARTIAL, a, n_col_tiles);
+    launch_gemm(s, epi, a, n_col_tiles);
+  } else {
+    a.ksplit = 1;
+    a.ws = nullptr;
+    launch_gemm(s, epi, a, n_col_tiles);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -33,7 +33,9 @@ struct Plan {
   float* V = nullptr;
   float* C = nullptr;
   float* Z[2] = {nullptr, nullptr};
-  float* Uf[2] = {nullptr, nullptr};  // ping-pong B-operand of the iteration (FP32)
+  float* Uf[2] = {nullptr, nullptr};       // ping-pong B-operand of the iteration (FP32)
+  uint16_t* Uh[2] = {nullptr, nullptr};    // its BF16 hi / lo split (BF16 precisions)
+  uint16_t* Ul[2] = {nullptr, nullptr};
   float* bb = nullptr;    // m_pad x N_pad copy of b
   float* aux = nullptr;   // 4 x (m_pad x N_pad) scratch
   float* pen = nullptr;   // beta (DALM) or xi (PALM) per column
@@ -41,6 +43,8 @@ struct Plan {
   float* zscale = nullptr;
   float* tscal = nullptr;
   float* partial = nullptr;
+  float* ws = nullptr;    // split-K workspace: ws_tiles x TILE x lds floats
+  int ws_tiles = 0, ks_target = 384, ks_max = 8;
   int* ints = nullptr;    // lists and counters
   long long* stat = nullptr;
   double* kkt_rbuf = nullptr;

@@ -37,12 +37,13 @@ Lists lists_of(Plan* p) {
   const int Np = p->N_pad;
   int* q = p->ints;
   Lists L;
-  L.state = q;
+  L.state = q;                                     // phase buffer 0 (buffer 1 at q + 5 Np + 256)
   L.iters = q + Np;
   L.status = q + 2 * Np;
   L.slot_col = q + 3 * Np;                         // Np + NPHASE*TILE entries
   L.phase_off = q + 4 * Np + NPHASE * TILE;        // NPHASE + 1 entries
   L.n_total = L.phase_off + NPHASE + 1;
+  L.cnt = L.n_total + 1;
   return L;
 }
 
@@ -160,10 +161,13 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     di.eps = eps;
     di.zscale = p->zscale;
     di.U = p->Uf[0];
+    di.Uhi = p->Uh[0];
+    di.Ulo = p->Ul[0];
     dalm_init_u(s, N, di);
   }
   const Lists L = lists_of(p);
-  init_lists(s, N, first, L, p->stat);
+  int* stbuf[2] = {L.state, p->ints + 5 * p->N_pad + 256};
+  init_lists(s, N, first, L, stbuf[1], p->stat);
 
   // tape: checkpoints of (W, V) every k iterations of a fixed-count solve
   const bool tape = fixed && p->d.record_tape;
@@ -185,6 +189,9 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
                           hipMemcpyDeviceToDevice, s));
   }
 
+  const float tol = fixed ? -1.0f : a.tol;
+  const float floors[NPHASE] = {1.0f, 4e-6f, 2e-6f};  // BF16 (never final), split BF16, FP32
+  float* part[2] = {p->partial, p->partial + (size_t)p->ntiles * NPART * p->N_pad};
   GemmArgs it{};
   it.A32 = p->P32;
   it.Ahi = p->Phi;
@@ -201,121 +208,185 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   it.W = p->W;
   it.C = p->C;
   it.beta = p->pen;
-  it.partial = p->partial;
   it.ldp = p->N_pad;
   it.n_l1 = p->n_l1;
   it.e0 = p12 ? nd : (1 << 30);
   it.zscale = p12 ? p->zscale : nullptr;
+  it.iters = L.iters;
+  it.status = L.status;
+  it.tp_tol = tol;
+  it.tp_sw = sw;
+  for (int q = 0; q < NPHASE; ++q) it.tp_floor[q] = floors[q];
+  it.tp_final = last;
+  it.eps = p12 ? eps : nullptr;
+  it.stat = p->stat;
+  it.ws = p->ws;
   DalmCheck ck{};
   ck.N = N;
-  ck.partial = p->partial;
   ck.ldp = p->N_pad;
   ck.ntiles = p->ntiles;
-  ck.tol = fixed ? -1.0f : a.tol;
-  ck.floor[PREC_BF16] = 1.0f;
-  ck.floor[PREC_BF16X3] = 4e-6f;
-  ck.floor[PREC_F32] = 2e-6f;
+  ck.tol = tol;
+  for (int q = 0; q < NPHASE; ++q) ck.floor[q] = floors[q];
   ck.sw = sw;
   ck.final_phase = last;
   ck.L = L;
   ck.eps = eps;
   ck.beta = p->pen;
-  ck.zscale = p12 ? p->zscale : nullptr;
   ck.stat = p->stat;
   P12Fix fx{};
   fx.n = n;
   fx.e0 = nd;
   fx.lds = lds;
+  fx.ldp = p->N_pad;
+  fx.ntiles = p->ntiles;
   fx.slot_col = L.slot_col;
   fx.phase_off = L.phase_off;
   fx.V = p->V;
   fx.W = p->W;
   fx.beta = p->pen;
-  fx.zscale = p->zscale;
+  fx.eps = eps;
 
-  constexpr int BLK = 16;  // iterations per graph replay / host poll (even)
+  constexpr int BLK = 16;  // iterations per host poll (and per graph replay; even)
   const bool timing = p->d.time_kernels != 0;
   std::vector<hipEvent_t> ev;
   if (timing) {
     ev.resize(2 * BLK);
     for (auto& e : ev) L1_HIP(hipEventCreate(&e));
   }
-  auto one_iter = [&](int t, int cur) {
+  // Launch shape of a block of iterations, from the number of unfinished
+  // instances polled before it (the count only shrinks inside a block):
+  // split the K range when few column tiles are active, so that enough
+  // workgroups run and each walks a shorter chain of K slices.
+  const int RT = p->n_pad / TILE, nk64 = p->n_pad / 64;
+  const int phases_used = (first == last) ? 1 : 2;
+  struct Shape {
+    int ctiles, ks;
+  };
+  auto shape_for = [&](int active) {
+    Shape sh;
+    sh.ctiles = col_tiles_for(active);
+    const int est = (active + TILE - 1) / TILE + phases_used - 1;
+    int ks = (p->ks_target + RT * est - 1) / (RT * est);
+    ks = std::min({ks, p->ks_max, nk64, std::max(1, p->ws_tiles / sh.ctiles)});
+    sh.ks = std::max(ks, 1);
+    return sh;
+  };
+  // iteration k (0-based) reads the phases and partial sums left by
+  // iteration k - 1 and writes its own into the other buffers
+  auto one_iter = [&](int k, int t, const Shape& sh) {
+    const int cur = k & 1;
     it.B = p->Uf[cur];
+    it.Bhi = p->Uh[cur];
+    it.Blo = p->Ul[cur];
     it.U = p->Uf[1 - cur];
+    it.Uhi = p->Uh[1 - cur];
+    it.Ulo = p->Ul[1 - cur];
+    it.state_in = stbuf[cur];
+    it.state_out = stbuf[1 - cur];
+    it.prev_partial = (k == 0) ? nullptr : part[1 - cur];
+    it.partial = part[cur];
     if (timing) L1_HIP(hipEventRecord(ev[2 * t], s));
-    launch_gemm(s, EPI_DALM, it, ctiles);
+    launch_product(s, EPI_DALM, it, sh.ctiles, sh.ks);
     if (timing) L1_HIP(hipEventRecord(ev[2 * t + 1], s));
-    dalm_check(s, ck);
     if (p12) {
+      fx.state = stbuf[1 - cur];
+      fx.partial = part[cur];
       fx.U = p->Uf[1 - cur];
-      p12_fix(s, ntc * TILE + NPHASE * TILE, fx);
+      fx.Uhi = p->Uh[1 - cur];
+      fx.Ulo = p->Ul[1 - cur];
+      p12_fix(s, sh.ctiles * TILE, fx);
     }
   };
+  // the phases after iteration k live in stbuf[(k + 1) & 1]
+  auto compact_after = [&](int k) {
+    const int nb = (k + 1) & 1;
+    ck.L.state = stbuf[nb];
+    ck.state_other = stbuf[1 - nb];
+    dalm_compact(s, ck);
+  };
 
-  // events recorded inside a captured graph cannot be timed, so timing runs uncaptured
-  bool use_graph = graphs_enabled() && !tape && !timing && cap >= 4 * BLK;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  if (use_graph) {
+  // captured blocks of BLK iterations, one per launch shape met; the first
+  // block (no test in its first launch), timing and tape recording run
+  // uncaptured (events inside a graph cannot be timed)
+  struct Captured {
+    Shape sh;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<Captured> graphs;
+  bool graphs_ok = graphs_enabled() && !tape && !timing && cap >= 4 * BLK;
+  auto graph_for = [&](const Shape& sh) -> hipGraphExec_t {
+    for (auto& c : graphs)
+      if (c.sh.ctiles == sh.ctiles && c.sh.ks == sh.ks) return c.x;
+    Captured c{sh, nullptr, nullptr};
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       try {
-        for (int t = 0; t < BLK; ++t) one_iter(t, t & 1);
+        for (int t = 0; t < BLK; ++t) one_iter(BLK + t, t, sh);  // any k > 0 of even block start
+        compact_after(2 * BLK - 1);
       } catch (const Fail&) {
         ok = false;
       }
-      hipError_t e = hipStreamEndCapture(s, &graph);
-      ok = ok && e == hipSuccess &&
-           hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+      const hipError_t e = hipStreamEndCapture(s, &c.g);
+      ok = ok && e == hipSuccess && hipGraphInstantiate(&c.x, c.g, nullptr, nullptr, 0) == hipSuccess;
     }
     if (!ok) {
       (void)hipGetLastError();
-      if (gexec) (void)hipGraphExecDestroy(gexec);
-      if (graph) (void)hipGraphDestroy(graph);
-      gexec = nullptr;
-      graph = nullptr;
-      use_graph = false;
+      if (c.x) (void)hipGraphExecDestroy(c.x);
+      if (c.g) (void)hipGraphDestroy(c.g);
+      return nullptr;
     }
-  }
-  long long hstat[8] = {0}, prev_any = 0;
+    graphs.push_back(c);
+    return c.x;
+  };
+  auto release = [&]() {
+    for (auto& c : graphs) {
+      (void)hipGraphExecDestroy(c.x);
+      (void)hipGraphDestroy(c.g);
+    }
+    graphs.clear();
+    for (auto e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  };
+
+  long long hstat[8] = {0}, prev_max = 0;
   double timed_ms = 0.0;
   long long timed_n = 0;
-  int done = 0, cur = 0;
+  int done = 0, active = N;
   try {
     while (done < cap) {
       const int blk = std::min(BLK, cap - done);
-      if (tape) {
+      const Shape sh = shape_for(active);
+      hipGraphExec_t gx = nullptr;
+      if (graphs_ok && blk == BLK && done > 0) {
+        gx = graph_for(sh);
+        if (!gx) graphs_ok = false;
+      }
+      if (gx) {
+        L1_HIP(hipGraphLaunch(gx, s));
+      } else {
         for (int t = 0; t < blk; ++t) {
           const int k = done + t;
-          if (k % every == 0) {
+          if (tape && k % every == 0) {
             const int ci = k / every;
             L1_HIP(hipMemcpyAsync(p->tape[2 * ci], p->W, sizeof(float) * (size_t)lds * N,
                                   hipMemcpyDeviceToDevice, s));
             L1_HIP(hipMemcpyAsync(p->tape[2 * ci + 1], p->V, sizeof(float) * (size_t)lds * N,
                                   hipMemcpyDeviceToDevice, s));
           }
-          one_iter(t, cur);
-          cur ^= 1;
+          one_iter(k, t, sh);
         }
-      } else if (gexec && blk == BLK && cur == 0) {
-        L1_HIP(hipGraphLaunch(gexec, s));
-      } else {
-        for (int t = 0; t < blk; ++t) {
-          one_iter(t, cur);
-          cur ^= 1;
-        }
+        compact_after(done + blk - 1);
       }
       done += blk;
       L1_HIP(hipMemcpyAsync(p->h_total, L.n_total, sizeof(int), hipMemcpyDeviceToHost, s));
-      if (timing)
-        L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
+      L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
       L1_HIP(hipStreamSynchronize(s));
+      active = *p->h_total;
       if (timing) {
-        // launches of this block that had work come first (work only shrinks)
-        const long long any = hstat[6];
-        const int with_work = (int)std::min<long long>(any - prev_any, blk);
-        prev_any = any;
+        // launches of this block that had work come first (work only shrinks);
+        // their count is the growth of the largest iteration count
+        const int with_work = (int)std::min<long long>(hstat[7] - prev_max, blk);
         for (int t = 0; t < with_work; ++t) {
           float ms = 0.0f;
           L1_HIP(hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]));
@@ -323,17 +394,23 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           ++timed_n;
         }
       }
-      if (!fixed && *p->h_total == 0) break;
+      prev_max = hstat[7];
+      if (!fixed && active == 0) break;
+      if (active == 0) active = 1;
     }
   } catch (...) {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    for (auto e : ev) (void)hipEventDestroy(e);
+    release();
     throw;
   }
-  if (gexec) L1_HIP(hipGraphExecDestroy(gexec));
-  if (graph) L1_HIP(hipGraphDestroy(graph));
-  for (auto e : ev) L1_HIP(hipEventDestroy(e));
+  release();
+  // the test of the last iteration (its launch only tested the one before)
+  {
+    const int klast = done - 1;
+    ck.L.state = stbuf[(klast + 1) & 1];
+    ck.partial = part[klast & 1];
+    dalm_final_test(s, ck);
+  }
+  L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
 
   // outputs
   copy_block(s, nd, N, p->W, lds, 0, a.x, a.ldx);
@@ -358,9 +435,8 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     }
   }
   finish_status(s, N, fixed ? cap : 0, L.iters, L.status, a.iters, a.status);
-  L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
   L1_HIP(hipStreamSynchronize(s));
-  // stats: header order FP32, BF16, split; internal phase order BF16, split, FP32
+  // stats: header order FP32, BF16, split; internal precision order BF16, split, FP32
   const int map[3] = {PREC_F32, PREC_BF16, PREC_BF16X3};
   for (int i = 0; i < 14; ++i) p->last_stats[i] = 0.0;
   for (int i = 0; i < 3; ++i) {
@@ -369,7 +445,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   }
   p->last_stats[6] = timed_ms;
   p->last_stats[7] = (double)timed_n;
-  p->last_stats[8] = (double)std::min(done, cap);
+  p->last_stats[8] = (double)hstat[7];
   p->last_stats[9] =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
 }

@@ -16,6 +16,7 @@ struct Lists {
   int* slot_col;    // N_pad + NPHASE*TILE entries
   int* phase_off;   // NPHASE + 1 entries
   int* n_total;     // number of unfinished instances (read by the host)
+  int* cnt;         // NPHASE entries: instances per phase in the current lists
 };
 
 struct DalmInit {
@@ -26,39 +27,51 @@ struct DalmInit {
   const float* eps;
   float* zscale;
   float* U;
+  uint16_t* Uhi;   // optional BF16 split of U
+  uint16_t* Ulo;
 };
 
 struct DalmCheck {
   int N;
-  const float* partial;
+  const float* partial;  // partial sums of the iteration to test (final test)
   int ldp, ntiles;
-  float tol;            // < 0: never converge (fixed iteration count)
-  float floor[NPHASE];  // the final test uses max(tol, floor[phase])
-  float sw;             // exit threshold of a non-final phase
+  float tol;             // < 0: never converge (fixed iteration count)
+  float floor[NPHASE];   // the final test uses max(tol, floor[phase])
+  float sw;              // exit threshold of a non-final phase
   int final_phase;
-  Lists L;
-  const float* eps;     // P_{1,2} only (with zscale)
+  Lists L;               // L.state: the current phase buffer
+  int* state_other;      // the other phase buffer (compaction copies into it)
+  const float* eps;      // P_{1,2} radii
   const float* beta;
-  float* zscale;
-  long long* stat;      // [p] launches with work in phase p, [3 + p] summed active columns
+  long long* stat;       // [7] = largest per-instance iteration count
 };
 
 struct P12Fix {
-  int n, e0, lds;
+  int n, e0, lds, ldp, ntiles;
   const int* slot_col;
   const int* phase_off;
+  const int* state;       // phases after the launch
+  const float* partial;   // partial sums of the launch (ball block norm)
   const float* V;
   const float* W;
   const float* beta;
-  const float* zscale;
+  const float* eps;
   float* U;
+  uint16_t* Uhi;          // optional BF16 split of U
+  uint16_t* Ulo;
 };
 
 void penalties(hipStream_t s, int N, int m, const float* b, int ldb, float fixed, int mode,
                float* pen, float* ipen);
 void dalm_init_u(hipStream_t s, int N, const DalmInit& a);
-void init_lists(hipStream_t s, int N, int phase0, const Lists& L, long long* stat);
-void dalm_check(hipStream_t s, const DalmCheck& a);
+void init_lists(hipStream_t s, int N, int phase0, const Lists& L, int* state_other,
+                long long* stat);
+// Compaction of the unfinished instances into the phase segments of the
+// slot list (one workgroup); also copies the phases into state_other.
+void dalm_compact(hipStream_t s, const DalmCheck& a);
+// Convergence test of the last iteration (the iteration launches test the
+// previous one in their prologue).
+void dalm_final_test(hipStream_t s, const DalmCheck& a);
 void p12_fix(hipStream_t s, int n_blocks, const P12Fix& a);
 void copy_block(hipStream_t s, int rows, int N, const float* src, int lds, int r0, float* dst,
                 int ldd);

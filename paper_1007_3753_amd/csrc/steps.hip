@@ -2,8 +2,26 @@
 // z/u, the convergence test with active-list compaction, the P_{1,2} block
 // prox fix-up, PALM's outer-step elementwise work, and output extraction.
 #include "steps.h"
+#include "dalm_test.h"
 
 namespace l1 {
+
+__device__ inline uint16_t f2bf_s(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f_s(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+// the iterate as FP32 and, when requested, as a BF16 hi / lo split
+__device__ inline void put_u(float* U, uint16_t* Uhi, uint16_t* Ulo, long idx, float u) {
+  U[idx] = u;
+  if (Uhi) {
+    const uint16_t h = f2bf_s(u);
+    Uhi[idx] = h;
+    Ulo[idx] = f2bf_s(u - bf2f_s(h));
+  }
+}
 
 __device__ float wg_sum(float v, float* sh) {
   sh[threadIdx.x] = v;
@@ -66,7 +84,7 @@ __global__ __launch_bounds__(256) void dalm_init_u_kernel(DalmInit a) {
   for (int i = threadIdx.x; i < a.n_pad; i += 256) {
     const float s = V[i] + W[i] * ib;
     const float z = (i >= a.e0) ? s * zs : fminf(fmaxf(s, -1.0f), 1.0f);
-    a.U[(long)c * a.lds + i] = z - W[i] * ib;
+    put_u(a.U, a.Uhi, a.Ulo, (long)c * a.lds + i, z - W[i] * ib);
   }
 }
 void dalm_init_u(hipStream_t s, int N, const DalmInit& a) {
@@ -76,10 +94,11 @@ void dalm_init_u(hipStream_t s, int N, const DalmInit& a) {
 }
 
 // ---- lists -------------------------------------------------------------------
-__global__ void init_lists_kernel(int N, int phase0, Lists L, long long* stat) {
+__global__ void init_lists_kernel(int N, int phase0, Lists L, int* state_other, long long* stat) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < N) {
     L.state[c] = phase0;
+    state_other[c] = phase0;
     L.iters[c] = 0;
     L.status[c] = L1_MAXITER;
   }
@@ -87,13 +106,15 @@ __global__ void init_lists_kernel(int N, int phase0, Lists L, long long* stat) {
   if (c < npad) L.slot_col[c] = (c < N) ? c : -1;
   if (c == 0) {
     for (int p = 0; p <= NPHASE; ++p) L.phase_off[p] = (p <= phase0) ? 0 : npad;
+    for (int p = 0; p < NPHASE; ++p) L.cnt[p] = (p == phase0) ? N : 0;
     *L.n_total = N;
     for (int i = 0; i < 8; ++i) stat[i] = 0;
   }
 }
-void init_lists(hipStream_t s, int N, int phase0, const Lists& L, long long* stat) {
+void init_lists(hipStream_t s, int N, int phase0, const Lists& L, int* state_other,
+                long long* stat) {
   const int npad = (N + TILE - 1) / TILE * TILE;
-  init_lists_kernel<<<(npad + 255) / 256, 256, 0, s>>>(N, phase0, L, stat);
+  init_lists_kernel<<<(npad + 255) / 256, 256, 0, s>>>(N, phase0, L, state_other, stat);
   L1_HIP(hipGetLastError());
 }
 
@@ -114,70 +135,26 @@ __device__ int compact_pos(bool flag, int* wave_tot, int* total_out) {
   return off + before;
 }
 
-// ---- DALM convergence test and compaction (one workgroup) -------------------
-__global__ __launch_bounds__(1024) void dalm_check_kernel(DalmCheck a) {
+__global__ __launch_bounds__(1024) void dalm_compact_kernel(DalmCheck a) {
   __shared__ int wt[16];
-  __shared__ int cnt[NPHASE], before[NPHASE];
-  if (threadIdx.x < NPHASE) {
-    cnt[threadIdx.x] = 0;
-    before[threadIdx.x] = 0;
-  }
+  __shared__ int cnt[NPHASE], mx;
+  if (threadIdx.x < NPHASE) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) mx = 0;
   __syncthreads();
-  // pass 1: tests and state transitions
-  const float sw2 = a.sw * a.sw;
-  int mycnt[NPHASE] = {0, 0, 0}, mybefore[NPHASE] = {0, 0, 0};
+  int my[NPHASE] = {0, 0, 0}, mymax = 0;
   for (int c = threadIdx.x; c < a.N; c += 1024) {
-    int st = a.L.state[c];
-    if (st >= NPHASE) continue;
-    mybefore[st] += 1;
-    float d2 = 0.f, w2 = 0.f, l1 = 0.f, gp = 0.f, se = 0.f;
-    for (int t = 0; t < a.ntiles; ++t) {
-      const float* p = a.partial + (long)t * NPART * a.ldp + c;
-      d2 += p[0];
-      w2 += p[a.ldp];
-      l1 += p[2 * (long)a.ldp];
-      gp += p[3 * (long)a.ldp];
-      se += p[4 * (long)a.ldp];
-    }
-    a.L.iters[c] += 1;
-    const float gap = fabsf(gp);  // sum of |w_i| (1 - sign(w_i) v_i) over the l1 rows
-    const bool finite = isfinite(d2) && isfinite(w2) && isfinite(gap);
-    if (!finite) {
-      st = NPHASE;
-      a.L.status[c] = L1_NONFINITE;
-    } else if (st != a.final_phase) {
-      if (d2 <= sw2 * w2 && gap <= a.sw * l1) ++st;
-    } else if (a.tol >= 0.0f) {
-      const float t = fmaxf(a.tol, a.floor[st]);
-      if (d2 <= t * t * w2 && gap <= t * l1) {
-        st = NPHASE;
-        a.L.status[c] = L1_CONVERGED;
-      }
-    }
-    if (a.zscale && st < NPHASE) {
-      const float tau = a.eps[c] / a.beta[c];
-      a.zscale[c] = (se > 0.0f) ? fmaxf(0.0f, 1.0f - tau / sqrtf(se)) : 0.0f;
-    }
-    a.L.state[c] = st;
-    if (st < NPHASE) mycnt[st] += 1;
+    const int st = a.L.state[c];
+    a.state_other[c] = st;
+    if (st < NPHASE) my[st] += 1;
+    mymax = max(mymax, a.L.iters[c]);
   }
-  for (int p = 0; p < NPHASE; ++p) {
-    if (mycnt[p]) atomicAdd(&cnt[p], mycnt[p]);
-    if (mybefore[p]) atomicAdd(&before[p], mybefore[p]);
-  }
+  for (int p = 0; p < NPHASE; ++p)
+    if (my[p]) atomicAdd(&cnt[p], my[p]);
+  atomicMax(&mx, mymax);
   __syncthreads();
-  if (threadIdx.x == 0 && a.stat) {
-    for (int p = 0; p < NPHASE; ++p)
-      if (before[p] > 0) {
-        a.stat[p] += 1;
-        a.stat[3 + p] += before[p];
-      }
-    if (before[0] + before[1] + before[2] > 0) a.stat[6] += 1;
-  }
   int off[NPHASE + 1];
   off[0] = 0;
   for (int p = 0; p < NPHASE; ++p) off[p + 1] = off[p] + (cnt[p] + TILE - 1) / TILE * TILE;
-  // pass 2: stable compaction into the phase segments
   int base[NPHASE] = {0, 0, 0};
   for (int c0 = 0; c0 < a.N; c0 += 1024) {
     const int c = c0 + threadIdx.x;
@@ -189,16 +166,39 @@ __global__ __launch_bounds__(1024) void dalm_check_kernel(DalmCheck a) {
       base[p] += tot;
     }
   }
-  // idle padding slots
   for (int p = 0; p < NPHASE; ++p)
     for (int s = off[p] + cnt[p] + threadIdx.x; s < off[p + 1]; s += 1024) a.L.slot_col[s] = -1;
   if (threadIdx.x == 0) {
     for (int p = 0; p <= NPHASE; ++p) a.L.phase_off[p] = off[p];
+    for (int p = 0; p < NPHASE; ++p) a.L.cnt[p] = cnt[p];
     *a.L.n_total = cnt[0] + cnt[1] + cnt[2];
+    if (a.stat) a.stat[7] = mx;
   }
 }
-void dalm_check(hipStream_t s, const DalmCheck& a) {
-  dalm_check_kernel<<<1, 1024, 0, s>>>(a);
+void dalm_compact(hipStream_t s, const DalmCheck& a) {
+  dalm_compact_kernel<<<1, 1024, 0, s>>>(a);
+  L1_HIP(hipGetLastError());
+}
+
+// the test of the last iteration: 4 lanes per instance, no iteration counted
+__global__ __launch_bounds__(256) void dalm_final_test_kernel(DalmCheck a) {
+  const int c = blockIdx.x * 64 + (threadIdx.x >> 2), part = threadIdx.x & 3;
+  const int st0 = (c < a.N) ? a.L.state[c] : NPHASE;
+  float sm[NPART];
+  column_sums(a.partial, a.ldp, a.ntiles, c, st0 < NPHASE, part, sm);
+  if (part != 0 || st0 >= NPHASE) return;
+  TestParams tp;
+  tp.tol = a.tol;
+  tp.sw = a.sw;
+  tp.final_phase = a.final_phase;
+  for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.floor[q];
+  int status = L1_MAXITER;
+  const int st = decide(tp, st0, sm, &status);
+  if (st != st0) a.L.state[c] = st;
+  if (st >= NPHASE) a.L.status[c] = status;
+}
+void dalm_final_test(hipStream_t s, const DalmCheck& a) {
+  dalm_final_test_kernel<<<(a.N + 63) / 64, 256, 0, s>>>(a);
   L1_HIP(hipGetLastError());
 }
 
@@ -207,14 +207,22 @@ __global__ __launch_bounds__(256) void p12_fix_kernel(P12Fix a) {
   const int slot = blockIdx.x;
   if (slot >= a.phase_off[NPHASE]) return;
   const int c = a.slot_col[slot];
-  if (c < 0) return;
+  if (c < 0 || a.state[c] >= NPHASE) return;
+  __shared__ float sh_scale;
+  if (threadIdx.x < 64) {
+    // the same sums, in the same order, as the next launch's prologue
+    float sm[NPART];
+    column_sums(a.partial, a.ldp, a.ntiles, c, true, threadIdx.x & 3, sm);
+    if (threadIdx.x == 0) sh_scale = ball_scale(sm[4], a.eps[c], a.beta[c]);
+  }
+  __syncthreads();
   const float ib = 1.0f / a.beta[c];
-  const float zs = a.zscale[c];
+  const float zs = sh_scale;
   for (int i = a.e0 + threadIdx.x; i < a.n; i += 256) {
     const long idx = (long)c * a.lds + i;
     const float w = a.W[idx];
     const float s2 = a.V[idx] + w * ib;
-    a.U[idx] = s2 * zs - w * ib;
+    put_u(a.U, a.Uhi, a.Ulo, idx, s2 * zs - w * ib);
   }
 }
 void p12_fix(hipStream_t s, int n_blocks, const P12Fix& a) {
