@@ -63,7 +63,9 @@ typedef enum { L1_DALM = 0, L1_PALM = 1 } l1_method;
  *                  accumulation, ~16 significant bits) until convergence.
  *                  An instance can only be declared converged in the split
  *                  phase.
- *   L1_BF16X3      split-BF16 products for every iteration.                 */
+ *   L1_BF16X3      split-BF16 products for every iteration.
+ * PALM runs its FISTA products (with A^T A) in split BF16 under either BF16
+ * mode, and its A x / A^T c products in FP32.                               */
 typedef enum { L1_FP32 = 0, L1_BF16_REFINE = 1, L1_BF16X3 = 2 } l1_precision;
 
 typedef struct l1_alm_plan_s* l1_alm_plan_t;   /* opaque, owned by the library */
@@ -117,7 +119,9 @@ int l1_alm_plan(const l1_alm_desc* desc, const float* A_dev, void* stream,
  *             products' arithmetic (FP32 2e-6, split BF16 4e-6).
  *   max_iter  > 0: iteration cap (DALM iterations / PALM outer steps);
  *             < 0: run exactly -max_iter iterations with no stopping test
- *             (the unrolled map used by l1_alm_backward; DALM only).
+ *             (DALM: the unrolled map used by l1_alm_backward; PALM: exactly
+ *             -max_iter outer steps of exactly desc.max_inner FISTA steps).
+ *             PALM ignores w0_dev / y0_dev (must be NULL) and writes no y.
  *   w0_dev, y0_dev  DALM warm start (n_full x N with ld n_full, m x N with
  *             ld m), or NULL for w0 = 0, y0 = 0 (Algorithm 2 input).
  *   x_dev     n_dict x N output, leading dimension ldx >= n_dict.
@@ -165,10 +169,11 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
  *   [6]     total duration (ms) of the timed product launches that had work
  *           (desc.time_kernels = 1; HIP events around each launch), else 0
  *   [7]     number of such timed launches
- *   [8]     iterations run (the largest per-instance count)
+ *   [8]     iterations run (the largest per-instance count; PALM: outer steps)
  *   [9]     wall time of the call on the host (ms)
  *   [10]    one-time plan construction time (ms, host wall clock)
- *   [11..13] reserved (0)
+ *   [11]    PALM: FISTA product launches issued (summed over outer steps)
+ *   [12..13] reserved (0)
  * The tolerance floors used by the stopping test are FP32 2e-6 and split
  * BF16 4e-6 (the level where rounding noise stalls the test).             */
 int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n);

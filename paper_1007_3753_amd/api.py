@@ -105,7 +105,8 @@ class Plan:
         N = bc.shape[0]
         dev = bc.device
         x = torch.empty(N, self.n_dict, device=dev, dtype=torch.float32)
-        e = torch.empty(N, self.m, device=dev, dtype=torch.float32) if self.split else None
+        has_e = self.split or (self.method == "palm" and self.problem == "qp")
+        e = torch.empty(N, self.m, device=dev, dtype=torch.float32) if has_e else None
         y = torch.empty(N, self.m, device=dev, dtype=torch.float32) if (want_y and self.method == "dalm") else None
         iters = torch.empty(N, device=dev, dtype=torch.int32)
         status = torch.empty(N, device=dev, dtype=torch.int32)
@@ -139,7 +140,8 @@ class Plan:
         return rep
 
     STAT_KEYS = ("launch_fp32", "launch_bf16", "launch_split", "cols_fp32", "cols_bf16",
-                 "cols_split", "timed_ms", "timed_launches", "iterations", "solve_ms", "plan_ms")
+                 "cols_split", "timed_ms", "timed_launches", "iterations", "solve_ms", "plan_ms",
+                 "inner_iterations")
 
     def last_stats(self):
         out = (ctypes.c_double * 14)()

@@ -142,6 +142,7 @@ struct GemmArgs {
   const float* prev_partial;   // null: no test (first iteration of a solve)
   float tp_tol, tp_sw, tp_floor[3];
   int tp_final;
+  int test_kind;               // 0: DALM test (decide()), 1: FISTA inner test (relative change)
   const float* eps;            // P_{1,2} radii (the ball scale comes from prev_partial)
   long long* stat;             // [3 + prec] += live columns, [prec] += column tiles
 };

@@ -289,7 +289,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     column_sums(a.prev_partial, a.ldp, RT, col, live0 && a.prev_partial, part, sm);
     int st = st0, stat_new = L1_MAXITER;
     float zs = 1.0f;
-    if (live0 && a.prev_partial) {
+    if (live0 && a.prev_partial && a.test_kind == 1) {
+      // FISTA inner loop: stop on the relative change of the shrink output
+      const float t = a.tp_tol;
+      if (!(isfinite(sm[0]) && isfinite(sm[1]))) st = NPHASE;
+      else if (t >= 0.0f && sm[0] <= t * t * sm[1]) st = NPHASE;
+    } else if (live0 && a.prev_partial) {
       TestParams tp;
       tp.tol = a.tp_tol;
       tp.sw = a.tp_sw;
@@ -312,8 +317,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       if (EPI != EPI_PARTIAL && rt == 0) {
         a.state_out[col] = st;
         if (live0) {
-          if (st >= NPHASE) a.status[col] = stat_new;
-          else a.iters[col] += 1;
+          if (st >= NPHASE) {
+            if (a.status) a.status[col] = stat_new;
+          } else {
+            a.iters[col] += 1;
+          }
         }
       }
     }
@@ -463,6 +471,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
           part[bj][1] += wn * wn;
         }
         *reinterpret_cast<f4*>(a.out + idx) = un4;  // next FISTA point
+        if (a.Uhi) {
+          us4 h, l;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint16_t hb = f2bf(un4[r]);
+            h[r] = hb;
+            l[r] = f2bf(un4[r] - bf2f(hb));
+          }
+          *reinterpret_cast<us4*>(a.Uhi + idx) = h;
+          *reinterpret_cast<us4*>(a.Ulo + idx) = l;
+        }
       }
       *reinterpret_cast<f4*>(a.W + idx) = wn4;
     }

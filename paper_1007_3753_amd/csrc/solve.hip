@@ -266,7 +266,8 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     Shape sh;
     sh.ctiles = col_tiles_for(active);
     const int est = (active + TILE - 1) / TILE + phases_used - 1;
-    int ks = (p->ks_target + RT * est - 1) / (RT * est);
+    // split only when the launch would leave most compute units idle
+    int ks = (RT * est >= p->ks_target) ? 1 : (p->ks_target + RT * est - 1) / (RT * est);
     ks = std::min({ks, p->ks_max, nk64, std::max(1, p->ws_tiles / sh.ctiles)});
     sh.ks = std::max(ks, 1);
     return sh;
@@ -448,12 +449,6 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   p->last_stats[8] = (double)hstat[7];
   p->last_stats[9] =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-}
-
-void solve_palm(Plan* p, const SolveArgs& a) {
-  check_common(p, a);
-  set_error("PALM is not available in this build");
-  throw Fail{L1_EINVAL};
 }
 
 void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* gA,
