@@ -51,7 +51,7 @@ def parse():
                     help="instances whose x is compared with the exact LP optimum")
     ap.add_argument("--plain-instances", type=int, default=8,
                     help="instances solved one per launch with FP32 for the plain-path figure")
-    ap.add_argument("--cpu-instances", type=int, default=2,
+    ap.add_argument("--cpu-instances", type=int, default=4,
                     help="instances the FP64 CPU oracle solves for the cpu_baseline figure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -116,7 +116,7 @@ def main():
         step()
     torch.cuda.synchronize()
     agg = dict(timed_ms=0.0, timed_launches=0.0, launch_fp32=0.0, launch_bf16=0.0, launch_split=0.0,
-               cols_fp32=0.0, cols_bf16=0.0, cols_split=0.0)
+               cols_fp32=0.0, cols_bf16=0.0, cols_split=0.0, iterations=0.0)
     t_start = time.perf_counter()
     for _ in range(args.steps):
         r, rep = step()
@@ -146,7 +146,9 @@ def main():
     # and the BF16 split of u written (4 B) when a BF16 mode runs
     esize = {"fp32": 4, "bf16": 2, "split": 4}
     tot_cols = max(sum(cols.values()), 1.0)
-    op_bytes = nl * n_full * n_full * sum(esize[k] * cols[k] for k in cols) / tot_cols
+    # the operator is read once by every launch that had work (one per
+    # iteration of the slowest instance)
+    op_bytes = agg["iterations"] * n_full * n_full * sum(esize[k] * cols[k] for k in cols) / tot_cols
     low = args.precision != "fp32"
     bytes_total = op_bytes + n_full * sum(cols[k] * (esize[k] + 24 + (4 if low else 0)) for k in cols)
     t_mfma = sum(flops[k] / (PEAK_TFLOPS[k] * 1e12) for k in flops)
@@ -165,7 +167,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
     roof.update({
-        "kernel": "gemm_kernel<EPI_DALM>",
+        "kernel": "DALM iteration launch: gemm_kernel<EPI_DALM> (+ its split-K gemm_kernel<EPI_PARTIAL> "
+                  "launch when the active set is small, + 1/16 of a compaction)",
         "avg_launch_us": round(1e6 * kern_s / nl, 3),
         "launches_timed": int(agg["timed_launches"]),
         "algorithmic_flops_per_launch": round(tot_flops / nl),

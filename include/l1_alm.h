@@ -89,8 +89,8 @@ typedef struct {
   double refine_switch;  /* L1_BF16_REFINE: switch threshold (<= 0 -> 3e-3)           */
   int record_tape;       /* 1: fixed-count DALM solves keep checkpoints for backward */
   int checkpoint_every;  /* checkpoint spacing in iterations (<= 0 -> 10)            */
-  int time_kernels;      /* 1: time every per-iteration product launch with HIP
-                            events on the solve stream (see l1_alm_last_stats)      */
+  int time_kernels;      /* 1: time the DALM iteration loop with HIP events on the
+                            solve stream (see l1_alm_last_stats)                    */
 } l1_alm_desc;
 
 /* Build a plan for the dictionary A_dev (m x n_dict, column-major, leading
@@ -166,9 +166,10 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
  *           had work, summed over the launches, by the arithmetic of the
  *           tile: FP32, BF16, split BF16
  *   [3..5]  instances summed over those tiles and launches, by arithmetic
- *   [6]     total duration (ms) of the timed product launches that had work
- *           (desc.time_kernels = 1; HIP events around each launch), else 0
- *   [7]     number of such timed launches
+ *   [6]     DALM, desc.time_kernels = 1: duration (ms) of the iteration loop,
+ *           from HIP events on the solve stream around every block of 16
+ *           iteration launches (with their compaction); else 0
+ *   [7]     number of iteration launches inside those blocks
  *   [8]     iterations run (the largest per-instance count; PALM: outer steps)
  *   [9]     wall time of the call on the host (ms)
  *   [10]    one-time plan construction time (ms, host wall clock)

@@ -79,6 +79,7 @@ class Plan:
         d.record_tape, d.checkpoint_every = int(bool(record_tape)), int(checkpoint_every)
         d.time_kernels = int(bool(time_kernels))
         self.desc = d
+        self._tape_N = 0
         h = ctypes.c_void_p()
         if Ac.numel() == 0:
             Ac = torch.zeros(1, device=A.device)
@@ -121,8 +122,26 @@ class Plan:
             self.handle, _ptr(bc), self.m, N, _ptr(epsc), ctypes.c_float(tol), int(max_iter),
             _ptr(w0c), _ptr(y0c), _ptr(x), max(self.n_dict, 1), _ptr(e), self.m, _ptr(y), self.m,
             _ptr(iters), _ptr(status), _stream()))
+        if max_iter < 0 and self.desc.record_tape:
+            self._tape_N = N
         return SolveResult(x.t(), None if e is None else e.t(), None if y is None else y.t(),
                            iters, status)
+
+    def backward(self, gx, ge=None):
+        """Reverse-mode product of the last recorded fixed-count solve: given
+        the adjoints of its outputs x (n_dict, N) and e (m, N), returns
+        (gb (m, N), gA (m, n_dict)) = gradients with respect to b and the
+        dictionary."""
+        gxc = _colmajor(gx, self.n_dict)
+        N = self._tape_N or gxc.shape[0]
+        gec = _colmajor(ge, self.m) if (ge is not None and self.split) else None
+        if gxc.shape[0] != N or (gec is not None and gec.shape[0] != N):
+            raise ValueError("adjoints must have one column per recorded instance")
+        gb = torch.empty(N, self.m, device=gxc.device, dtype=torch.float32)
+        gA = torch.zeros(self.n_dict, self.m, device=gxc.device, dtype=torch.float32)
+        _lib.check(self.lib.l1_alm_backward(self.handle, _ptr(gxc), _ptr(gec), _ptr(gb), _ptr(gA),
+                                            _stream()))
+        return gb.t(), gA.t()
 
     def kkt(self, b, x, e=None, y=None, eps=None):
         """FP64 certificate per instance: (N, 4) float64 tensor of
@@ -147,3 +166,35 @@ class Plan:
         out = (ctypes.c_double * 14)()
         _lib.check(self.lib.l1_alm_last_stats(self.handle, out, 14))
         return dict(zip(self.STAT_KEYS, list(out)))
+
+
+class DALMUnrolled(torch.autograd.Function):
+    """``x, e = DALMUnrolled.apply(b, B, iters, checkpoint_every)``: exactly
+    ``iters`` dual ALM iterations (Algorithm 2) on the cross-and-bouquet
+    matrix [B, I] from w = 0, y = 0, as a differentiable map of b (m, N) and
+    B (m, n_B).  The forward solve and the backward pass both run in the
+    library (the backward recomputes the iterations from checkpoints kept
+    every ``checkpoint_every`` iterations); beta is the per-instance default
+    and is held constant."""
+
+    @staticmethod
+    def forward(ctx, b, B, iters=50, checkpoint_every=10):
+        b = b.detach()
+        B = B.detach()
+        plan = Plan(B, structure="cab", precision="fp32", max_batch=b.shape[1],
+                    record_tape=True, checkpoint_every=int(checkpoint_every))
+        r = plan.solve(b, max_iter=-int(iters), want_y=False)
+        ctx.plan = plan
+        return r.x, r.e
+
+    @staticmethod
+    def backward(ctx, gx, ge):
+        plan = ctx.plan
+        if gx is None:
+            gx = torch.zeros(plan.n_dict, plan.max_batch, device=plan.device)
+        if ge is None:
+            ge = torch.zeros(plan.m, plan.max_batch, device=plan.device)
+        gb, gB = plan.backward(gx, ge)
+        ctx.plan = None
+        plan.close()
+        return gb, gB, None, None

@@ -53,8 +53,9 @@ struct Plan {
   double plan_ms = 0.0;
   // tape of the last recorded fixed-count solve
   std::vector<void*> tape;
-  int tape_N = 0, tape_K = 0, tape_every = 0;
-  float* tape_b = nullptr;
+  int tape_N = 0, tape_K = 0, tape_every = 0;   // tape_N = 0: no complete tape
+  float* tape_b = nullptr;    // b of the recorded solve (m_pad x N)
+  float* tape_pen = nullptr;  // its beta (N) and 1/beta (N)
 };
 
 struct SolveArgs {
@@ -80,6 +81,9 @@ struct SolveArgs {
 Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s);
 void destroy_plan(Plan* p);
 void solve_dalm(Plan* p, const SolveArgs& a);
+// K-range split of the DALM iteration product for `active` instances spread
+// over `phases_used` precision phases (1 = no split)
+int dalm_ksplit(const Plan* p, int active, int phases_used);
 void solve_palm(Plan* p, const SolveArgs& a);
 void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* gA,
                    hipStream_t s);

@@ -80,13 +80,24 @@ static void dalm_phases(int precision, bool fixed, int* first, int* last) {
   (void)fixed;
 }
 
+int dalm_ksplit(const Plan* p, int active, int phases_used) {
+  const int RT = p->n_pad / TILE, nk64 = p->n_pad / 64;
+  const int ctiles = col_tiles_for(active);
+  const int est = (active + TILE - 1) / TILE + phases_used - 1;
+  // split only when the launch would leave most compute units idle
+  int ks = (RT * est >= p->ks_target) ? 1 : (p->ks_target + RT * est - 1) / (RT * est);
+  ks = std::min({ks, p->ks_max, nk64, std::max(1, p->ws_tiles / ctiles)});
+  return std::max(ks, 1);
+}
+
 void solve_dalm(Plan* p, const SolveArgs& a) {
   check_common(p, a);
   if (a.N == 0) return;
   const auto t_start = std::chrono::steady_clock::now();
   const bool fixed = a.max_iter < 0;
-  L1_REQUIRE(!(fixed && p->d.record_tape) || p->d.structure == L1_CAB,
-             "recording a tape is supported for the cross-and-bouquet DALM");
+  L1_REQUIRE(!(fixed && p->d.record_tape) ||
+                 (p->d.problem != L1_P12 && p->d.precision == L1_FP32),
+             "recording a tape needs an FP32 plan for P1 or QP_lambda");
   const int cap = fixed ? -a.max_iter : a.max_iter;
   StreamGuard sg(a.s);
   hipStream_t s = sg.own;
@@ -176,17 +187,24 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     for (void* q : p->tape) (void)hipFree(q);
     p->tape.clear();
     const int nck = (cap + every - 1) / every;  // states at iterations 0, k, 2k, ... < cap
-    for (int i = 0; i < 2 * nck + 1; ++i) {
+    p->tape_N = 0;
+    for (int i = 0; i < 2 * nck + 2; ++i) {
       void* q = nullptr;
-      L1_HIP(hipMalloc(&q, sizeof(float) * (size_t)lds * N));
+      if (hipMalloc(&q, sizeof(float) * (size_t)lds * N) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("out of device memory for the tape");
+        throw Fail{L1_ENOMEM};
+      }
       p->tape.push_back(q);
     }
-    p->tape_N = N;
     p->tape_K = cap;
     p->tape_every = every;
-    p->tape_b = reinterpret_cast<float*>(p->tape.back());
+    p->tape_b = reinterpret_cast<float*>(p->tape[2 * nck]);      // b, ld m_pad
+    p->tape_pen = reinterpret_cast<float*>(p->tape[2 * nck + 1]);  // beta, 1/beta
     L1_HIP(hipMemcpyAsync(p->tape_b, p->bb, sizeof(float) * p->m_pad * N,
                           hipMemcpyDeviceToDevice, s));
+    L1_HIP(hipMemcpyAsync(p->tape_pen, p->pen, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
+    L1_HIP(hipMemcpyAsync(p->tape_pen + N, p->ipen, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
   }
 
   const float tol = fixed ? -1.0f : a.tol;
@@ -247,17 +265,19 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   fx.eps = eps;
 
   constexpr int BLK = 16;  // iterations per host poll (and per graph replay; even)
+  // time_kernels: HIP events on the solve stream around every block of BLK
+  // iterations (graph replay or uncaptured launches; the block's compaction
+  // included), so the timed launches run exactly as untimed ones do
   const bool timing = p->d.time_kernels != 0;
   std::vector<hipEvent_t> ev;
   if (timing) {
-    ev.resize(2 * BLK);
+    ev.resize(2);
     for (auto& e : ev) L1_HIP(hipEventCreate(&e));
   }
   // Launch shape of a block of iterations, from the number of unfinished
   // instances polled before it (the count only shrinks inside a block):
   // split the K range when few column tiles are active, so that enough
   // workgroups run and each walks a shorter chain of K slices.
-  const int RT = p->n_pad / TILE, nk64 = p->n_pad / 64;
   const int phases_used = (first == last) ? 1 : 2;
   struct Shape {
     int ctiles, ks;
@@ -265,16 +285,12 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   auto shape_for = [&](int active) {
     Shape sh;
     sh.ctiles = col_tiles_for(active);
-    const int est = (active + TILE - 1) / TILE + phases_used - 1;
-    // split only when the launch would leave most compute units idle
-    int ks = (RT * est >= p->ks_target) ? 1 : (p->ks_target + RT * est - 1) / (RT * est);
-    ks = std::min({ks, p->ks_max, nk64, std::max(1, p->ws_tiles / sh.ctiles)});
-    sh.ks = std::max(ks, 1);
+    sh.ks = dalm_ksplit(p, active, phases_used);
     return sh;
   };
   // iteration k (0-based) reads the phases and partial sums left by
   // iteration k - 1 and writes its own into the other buffers
-  auto one_iter = [&](int k, int t, const Shape& sh) {
+  auto one_iter = [&](int k, const Shape& sh) {
     const int cur = k & 1;
     it.B = p->Uf[cur];
     it.Bhi = p->Uh[cur];
@@ -286,9 +302,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     it.state_out = stbuf[1 - cur];
     it.prev_partial = (k == 0) ? nullptr : part[1 - cur];
     it.partial = part[cur];
-    if (timing) L1_HIP(hipEventRecord(ev[2 * t], s));
     launch_product(s, EPI_DALM, it, sh.ctiles, sh.ks);
-    if (timing) L1_HIP(hipEventRecord(ev[2 * t + 1], s));
     if (p12) {
       fx.state = stbuf[1 - cur];
       fx.partial = part[cur];
@@ -307,15 +321,14 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   };
 
   // captured blocks of BLK iterations, one per launch shape met; the first
-  // block (no test in its first launch), timing and tape recording run
-  // uncaptured (events inside a graph cannot be timed)
+  // block (no test in its first launch) and tape recording run uncaptured
   struct Captured {
     Shape sh;
     hipGraph_t g;
     hipGraphExec_t x;
   };
   std::vector<Captured> graphs;
-  bool graphs_ok = graphs_enabled() && !tape && !timing && cap >= 4 * BLK;
+  bool graphs_ok = graphs_enabled() && !tape && cap >= 4 * BLK;
   auto graph_for = [&](const Shape& sh) -> hipGraphExec_t {
     for (auto& c : graphs)
       if (c.sh.ctiles == sh.ctiles && c.sh.ks == sh.ks) return c.x;
@@ -323,7 +336,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       try {
-        for (int t = 0; t < BLK; ++t) one_iter(BLK + t, t, sh);  // any k > 0 of even block start
+        for (int t = 0; t < BLK; ++t) one_iter(BLK + t, sh);  // any k > 0 of even block start
         compact_after(2 * BLK - 1);
       } catch (const Fail&) {
         ok = false;
@@ -350,7 +363,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     ev.clear();
   };
 
-  long long hstat[8] = {0}, prev_max = 0;
+  long long hstat[8] = {0};
   double timed_ms = 0.0;
   long long timed_n = 0;
   int done = 0, active = N;
@@ -363,6 +376,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
         gx = graph_for(sh);
         if (!gx) graphs_ok = false;
       }
+      if (timing) L1_HIP(hipEventRecord(ev[0], s));
       if (gx) {
         L1_HIP(hipGraphLaunch(gx, s));
       } else {
@@ -375,27 +389,22 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
             L1_HIP(hipMemcpyAsync(p->tape[2 * ci + 1], p->V, sizeof(float) * (size_t)lds * N,
                                   hipMemcpyDeviceToDevice, s));
           }
-          one_iter(k, t, sh);
+          one_iter(k, sh);
         }
         compact_after(done + blk - 1);
       }
+      if (timing) L1_HIP(hipEventRecord(ev[1], s));
       done += blk;
       L1_HIP(hipMemcpyAsync(p->h_total, L.n_total, sizeof(int), hipMemcpyDeviceToHost, s));
       L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
       L1_HIP(hipStreamSynchronize(s));
       active = *p->h_total;
       if (timing) {
-        // launches of this block that had work come first (work only shrinks);
-        // their count is the growth of the largest iteration count
-        const int with_work = (int)std::min<long long>(hstat[7] - prev_max, blk);
-        for (int t = 0; t < with_work; ++t) {
-          float ms = 0.0f;
-          L1_HIP(hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]));
-          timed_ms += ms;
-          ++timed_n;
-        }
+        float ms = 0.0f;
+        L1_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        timed_ms += ms;
+        timed_n += blk;
       }
-      prev_max = hstat[7];
       if (!fixed && active == 0) break;
       if (active == 0) active = 1;
     }
@@ -437,6 +446,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   }
   finish_status(s, N, fixed ? cap : 0, L.iters, L.status, a.iters, a.status);
   L1_HIP(hipStreamSynchronize(s));
+  if (tape) p->tape_N = N;
   // stats: header order FP32, BF16, split; internal precision order BF16, split, FP32
   const int map[3] = {PREC_F32, PREC_BF16, PREC_BF16X3};
   for (int i = 0; i < 14; ++i) p->last_stats[i] = 0.0;
@@ -451,15 +461,5 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
 }
 
-void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* gA,
-                   hipStream_t s) {
-  (void)gx; (void)ge; (void)gb; (void)gA; (void)s;
-  if (p->tape.empty()) {
-    set_error("no recorded tape: solve with max_iter < 0 and desc.record_tape = 1 first");
-    throw Fail{L1_ENOTAPE};
-  }
-  set_error("backward is not available in this build");
-  throw Fail{L1_EINVAL};
-}
 
 }  // namespace l1

@@ -1,0 +1,126 @@
+"""GPU parity of the unrolled-DALM adjoint (l1_alm_backward) against the FP64
+oracle's plain reverse mode over a full tape.
+
+The forward map is a fixed number of Algorithm-2 iterations (Sec. V-B) on
+[B, I]; the GPU recomputes it segment by segment from checkpoints and runs
+the reverse steps in FP32 with FP64 accumulation of the dictionary terms.
+Bar: relative error <= 1e-3 on both gradients.
+"""
+import numpy as np
+import pytest
+
+from oracle import unrolled_vjp, unrolled_grad
+from workloads import cab_problem, tiny_dense
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _beta(b):
+    # the solver's default penalty ||b||_1 / m per instance
+    b = np.asarray(b, np.float64)
+    return np.abs(b).sum(axis=0) / b.shape[0]
+
+
+def _adjoints(n1, n2, N, key):
+    r = np.random.default_rng([10073753, 77, key])
+    return r.standard_normal((n1, N)), r.standard_normal((n2, N))
+
+
+@pytest.mark.parametrize("K,every", [(1, 10), (23, 10), (20, 4), (12, 12)])
+def test_cab_backward_matches_oracle(K, every):
+    P = cab_problem(m=130, classes=7, per_class=7, N=8, cfg=221)
+    from paper_1007_3753_amd import Plan
+    pl = Plan(torch.as_tensor(P.A, device="cuda"), structure="cab", max_batch=8,
+              record_tape=True, checkpoint_every=every)
+    b = torch.as_tensor(P.b, device="cuda")
+    pl.solve(b, max_iter=-K, want_y=False)
+    gx, ge = _adjoints(P.n_dict, P.m, 8, K)
+    gb, gB = pl.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"),
+                         torch.as_tensor(ge, dtype=torch.float32, device="cuda"))
+    gb_o, gB_o = unrolled_vjp(P.A, P.b, _beta(P.b), K, gx, ge)
+    assert _rel(_np(gb), gb_o) < 1e-3
+    assert _rel(_np(gB), gB_o) < 1e-3
+
+
+def test_dense_backward_equals_cab_on_the_same_matrix():
+    # a dense plan on the explicit matrix [B, I] runs the same iterations as
+    # the cross-and-bouquet plan on B; its gradient on the B block is gB
+    P = cab_problem(m=70, classes=5, per_class=6, N=5, cfg=222)
+    A = np.hstack([P.A, np.eye(P.m, dtype=np.float32)])
+    from paper_1007_3753_amd import Plan
+    pl = Plan(torch.as_tensor(A, device="cuda"), max_batch=5, record_tape=True,
+              checkpoint_every=6)
+    b = torch.as_tensor(P.b, device="cuda")
+    pl.solve(b, max_iter=-15, want_y=False)
+    gx, ge = _adjoints(P.n_dict, P.m, 5, 3)
+    gw = np.vstack([gx, ge])
+    gb, gA = pl.backward(torch.as_tensor(gw, dtype=torch.float32, device="cuda"))
+    gb_o, gB_o = unrolled_vjp(P.A, P.b, _beta(P.b), 15, gx, ge)
+    assert _rel(_np(gb), gb_o) < 1e-3
+    assert _rel(_np(gA)[:, :P.n_dict], gB_o) < 1e-3
+
+
+def test_unrolled_function_loss_gradient():
+    # autograd through DALMUnrolled and the class-residual loss (written here
+    # in torch, float64) against the oracle's gradient of the same loss
+    from paper_1007_3753_amd import DALMUnrolled
+    P = cab_problem(m=300, classes=20, per_class=7, N=32, cfg=223)
+    K = 50
+    B = torch.as_tensor(P.A, device="cuda").requires_grad_(True)
+    b = torch.as_tensor(P.b, device="cuda").requires_grad_(True)
+    x, e = DALMUnrolled.apply(b, B, K, 10)
+    C, pc = 20, 7
+    Bd, bd, xd, ed = B.double(), b.double(), x.double(), e.double()
+    res = torch.stack([torch.linalg.vector_norm(bd - ed - Bd[:, c * pc:(c + 1) * pc]
+                                                @ xd[c * pc:(c + 1) * pc], dim=0)
+                       for c in range(C)])
+    lab = torch.as_tensor(P.labels, device="cuda")
+    loss = torch.nn.functional.cross_entropy((-res).t(), lab)
+    loss.backward()
+    l_o, gb_o, gB_o = unrolled_grad(P.A, P.b, _beta(P.b), K, P.labels, pc)
+    assert abs(loss.item() - l_o) < 1e-4 * abs(l_o)
+    assert _rel(_np(b.grad), gb_o) < 1e-3
+    assert _rel(_np(B.grad), gB_o) < 1e-3
+
+
+def test_backward_full_size():
+    # 1200 x 700 dictionary, 256 instances, 50 iterations, checkpoints every 10
+    P = cab_problem(m=1200, classes=100, per_class=7, N=256, cfg=5)
+    from paper_1007_3753_amd import Plan
+    pl = Plan(torch.as_tensor(P.A, device="cuda"), structure="cab", max_batch=256,
+              record_tape=True, checkpoint_every=10)
+    pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-50, want_y=False)
+    gx, ge = _adjoints(P.n_dict, P.m, 256, 50)
+    gb, gB = pl.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"),
+                         torch.as_tensor(ge, dtype=torch.float32, device="cuda"))
+    gb_o, gB_o = unrolled_vjp(P.A, P.b, _beta(P.b), 50, gx, ge)
+    assert _rel(_np(gb), gb_o) < 1e-3
+    assert _rel(_np(gB), gB_o) < 1e-3
+
+
+def test_backward_without_tape_and_bad_plans():
+    from paper_1007_3753_amd import Plan, L1Error
+    P = tiny_dense(20, 60, N=2, key=31)
+    pl = Plan(torch.as_tensor(P.A, device="cuda"), max_batch=2)
+    with pytest.raises(L1Error) as ei:
+        pl.backward(torch.zeros(60, 2, device="cuda"))
+    assert ei.value.code == -6
+    # a solve with a stopping test records nothing
+    pl2 = Plan(torch.as_tensor(P.A, device="cuda"), max_batch=2, record_tape=True)
+    pl2.solve(torch.as_tensor(P.b, device="cuda"), tol=1e-4, max_iter=100)
+    with pytest.raises(L1Error):
+        pl2.backward(torch.zeros(60, 2, device="cuda"))
+    # recording needs FP32 products
+    pl3 = Plan(torch.as_tensor(P.A, device="cuda"), max_batch=2, record_tape=True,
+               precision="bf16x3")
+    with pytest.raises(L1Error):
+        pl3.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-5)
