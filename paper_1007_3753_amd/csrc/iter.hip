@@ -356,8 +356,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     } else {
       const int nk64 = a.K / 64;
       const int kb = (split * nk64) / ks, ke = ((split + 1) * nk64) / ks;
+      // slices in flight per arithmetic, from a sweep of 2..8 on the
+      // 1200 x 700 cross-and-bouquet operator (deeper split-BF16 prefetch
+      // makes the compiler serialise the loads)
       if (prec == PREC_F32) mainloop_f32<8>(a, i0, colidx, lds, acc, kb, ke);
-      else if (prec == PREC_BF16X3) mainloop_bf16<true, 4>(a, i0, colidx, lds, acc, kb, ke);
+      else if (prec == PREC_BF16X3) mainloop_bf16<true, 3>(a, i0, colidx, lds, acc, kb, ke);
       else mainloop_bf16<false, 4>(a, i0, colidx, lds, acc, kb, ke);
     }
     if (EPI == EPI_PARTIAL) {
