@@ -10,6 +10,7 @@
 
 #include "plan.h"
 #include "steps.h"
+#include "tail.h"
 
 namespace l1 {
 
@@ -367,10 +368,116 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   double timed_ms = 0.0;
   long long timed_n = 0;
   int done = 0, active = N;
+  // tail kernel: once few instances are left, the remaining iterations run
+  // in one cooperative launch (it also runs the test of the last iteration)
+  const int tail_f32 = (last == PREC_F32) ? 1 : 0;
+  const int tail_cap = tail_capacity(p->n_pad, tail_f32);
+  bool tail_ok = !tape && !p12 && (p->n_pad % (TAIL_ROWS * 4) == 0) && tail_cap >= 1 &&
+                 (tail_f32 || p->Phi != nullptr);
+  if (const char* e = std::getenv("L1ALM_TAIL")) tail_ok = tail_ok && e[0] != '0';
+  bool tail_done = false;
+  int tail_retry = 0;
   try {
     while (done < cap) {
       const int blk = std::min(BLK, cap - done);
       const Shape sh = shape_for(active);
+      if (tail_ok && done > 0 && done >= tail_retry && active <= tail_cap) {
+        const int G = p->n_pad / TAIL_ROWS;
+        const size_t xu = tail_f32 ? (size_t)TAIL_NC * p->n_pad * 4 : (size_t)TAIL_NC * p->n_pad * 2;
+        const size_t xp = (size_t)G * NPART * TAIL_NC * 4;
+        const size_t need = 256 + 4 * xu + 2 * xp + 1024;
+        unsigned char* pool = reinterpret_cast<unsigned char*>(tail_pool(need));
+        if (!pool) {
+          tail_ok = false;
+        } else {
+          TailArgs ta{};
+          ta.P32 = p->P32;
+          ta.Phi = p->Phi;
+          ta.Plo = p->Plo;
+          ta.n_pad = p->n_pad;
+          ta.n_l1 = p->n_l1;
+          ta.lds = lds;
+          ta.f32 = tail_f32;
+          ta.ncap = tail_cap;
+          ta.V = p->V;
+          ta.W = p->W;
+          ta.C = p->C;
+          ta.beta = p->pen;
+          ta.st[0] = stbuf[0];
+          ta.st[1] = stbuf[1];
+          ta.iters = L.iters;
+          ta.status = L.status;
+          ta.slot_col = L.slot_col;
+          ta.phase_off = L.phase_off;
+          ta.reg_partial = part[(done - 1) & 1];
+          ta.ldp = p->N_pad;
+          ta.ntiles = p->ntiles;
+          ta.U32 = p->Uf[done & 1];
+          ta.Uhi = p->Uh[done & 1];
+          ta.Ulo = p->Ul[done & 1];
+          ta.tp.tol = tol;
+          ta.tp.sw = sw;
+          ta.tp.final_phase = last;
+          for (int q = 0; q < NPHASE; ++q) ta.tp.floor[q] = floors[q];
+          unsigned char* c = pool + 256;
+          for (int b = 0; b < 2; ++b) {
+            if (tail_f32) {
+              ta.xu32[b] = reinterpret_cast<float*>(c);
+              c += xu;
+            } else {
+              ta.xuh[b] = reinterpret_cast<uint16_t*>(c);
+              c += xu;
+              ta.xul[b] = reinterpret_cast<uint16_t*>(c);
+              c += xu;
+            }
+          }
+          if (tail_f32) c += 2 * xu;
+          for (int b = 0; b < 2; ++b) {
+            ta.xpart[b] = reinterpret_cast<float*>(c);
+            c += xp;
+          }
+          ta.bar = reinterpret_cast<unsigned*>(pool);
+          ta.flag = reinterpret_cast<int*>(pool + 64);
+          ta.k0 = done;
+          ta.k_end = cap;
+          ta.ks = std::min(sh.ks, 8);
+          ta.stat = p->stat;
+          L1_HIP(hipMemsetAsync(pool, 0, 256, s));
+          if (timing) L1_HIP(hipEventRecord(ev[0], s));
+          if (launch_dalm_tail(s, ta)) {
+            if (timing) L1_HIP(hipEventRecord(ev[1], s));
+            L1_HIP(hipMemcpyAsync(p->h_total + 2, ta.flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+            L1_HIP(hipStreamSynchronize(s));
+            if (p->h_total[2] != 0) {
+              set_error("the grid barrier of the tail kernel gave up");
+              throw Fail{L1_EHIP};
+            }
+            const int kd = p->h_total[3];
+            if (kd == done) {
+              // declined (an instance is not yet in the final phase): go on
+              // launching per iteration and try again after the next block
+              tail_retry = done + BLK;
+            } else {
+            if (timing) {
+              float ms = 0.0f;
+              L1_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+              timed_ms += ms;
+              timed_n += kd - done;
+            }
+            done = kd;
+            tail_done = true;
+            compact_after(done - 1);
+            L1_HIP(hipMemcpyAsync(p->h_total, L.n_total, sizeof(int), hipMemcpyDeviceToHost, s));
+            L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
+            L1_HIP(hipStreamSynchronize(s));
+            active = *p->h_total;
+            break;
+            }
+          } else {
+            tail_ok = false;  // not co-resident on this device: launch per iteration
+          }
+        }
+      }
       hipGraphExec_t gx = nullptr;
       if (graphs_ok && blk == BLK && done > 0) {
         gx = graph_for(sh);
@@ -413,8 +520,9 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     throw;
   }
   release();
-  // the test of the last iteration (its launch only tested the one before)
-  {
+  // the test of the last iteration (its launch only tested the one before;
+  // the tail kernel runs it itself)
+  if (!tail_done) {
     const int klast = done - 1;
     ck.L.state = stbuf[(klast + 1) & 1];
     ck.partial = part[klast & 1];
