@@ -44,7 +44,7 @@ struct Plan {
   float* tscal = nullptr;
   float* partial = nullptr;
   float* ws = nullptr;    // split-K workspace: ws_tiles x TILE x lds floats
-  int ws_tiles = 0, ks_target = 192, ks_max = 8;
+  int ws_tiles = 0, ks_target = 192, ks_max = 4;
   int* ints = nullptr;    // lists and counters
   long long* stat = nullptr;
   double* kkt_rbuf = nullptr;
