@@ -76,7 +76,7 @@ def traffic_record(src_hash):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("iter.hip", "internal.h"):
+    for f in ("iter.hip", "internal.h", "tail.hip", "tail.h", "dalm_test.h"):
         h.update(open(os.path.join(ROOT, "paper_1007_3753_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -167,8 +167,9 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
     roof.update({
-        "kernel": "DALM iteration launch: gemm_kernel<EPI_DALM> (+ its split-K gemm_kernel<EPI_PARTIAL> "
-                  "launch when the active set is small, + 1/16 of a compaction)",
+        "kernel": "DALM iteration: gemm_kernel<EPI_DALM> (+ its split-K gemm_kernel<EPI_PARTIAL> "
+                  "launch when few column tiles are active, + 1/16 of a compaction), or one "
+                  "iteration of dalm_tail_kernel once at most 6 instances are left",
         "avg_launch_us": round(1e6 * kern_s / nl, 3),
         "launches_timed": int(agg["timed_launches"]),
         "algorithmic_flops_per_launch": round(tot_flops / nl),
