@@ -4,20 +4,23 @@
 // iteration path costs the kernel boundaries and the latency of one short
 // K chain, whatever the work.  This kernel runs the remaining iterations of
 // up to TAIL_NC instances in one cooperative launch:
-//   - workgroup g owns operator rows [16 g, 16 g + 16) and the matching rows
-//     of v and w for every listed instance, for the whole launch;
+//   - workgroup g owns operator rows [16 g, 16 g + 16), held in registers,
+//     and the matching entries of v and w of every listed instance, also in
+//     registers, for the whole launch;
 //   - per iteration it stages the B operand u (all rows, listed instances)
-//     in LDS, computes its 16 x 16 block of P u with the four waves each
-//     taking a quarter of K (MFMA, reduced in a fixed order), applies the
-//     dual ALM update of Algorithm 2 (the same arithmetic as the epilogue of
-//     the iteration GEMM), and publishes its rows of the next u and its
+//     in LDS, computes its 16 x 16 block of P u with the K range split as the
+//     iteration GEMM splits it (MFMA, parts added in a fixed order), applies
+//     the dual ALM update of Algorithm 2 (the same arithmetic as the epilogue
+//     of the iteration GEMM), and publishes its rows of the next u and its
 //     partial sums;
 //   - one grid barrier per iteration; the next iteration starts with the
 //     convergence test of this one (every workgroup computes it, so all take
 //     the same decisions).
-// The published data live in uncached device memory, so the barrier needs no
-// cache writeback or invalidation: each wave waits for its own stores, then
-// the workgroup adds to a counter and waits (bounded) for the grid.
+// Published data are written and read with agent-scope (sc1) accesses, which
+// the memory system keeps coherent across the XCDs' L2 caches, so the barrier
+// needs no L2 writeback or invalidation: each wave waits for its own stores,
+// the workgroup adds to a counter and waits (bounded) for the grid, then the
+// compute unit's L1 is dropped.
 #include <algorithm>
 #include <mutex>
 
@@ -41,35 +44,22 @@ __device__ inline float bf2f_t(uint16_t h) { return __uint_as_float(((uint32_t)h
 __device__ inline float clamp1_t(float x) { return fminf(fmaxf(x, -1.0f), 1.0f); }
 __device__ inline u4 ld16(const void* p) { return *reinterpret_cast<const u4*>(p); }
 
-// Published data are read and written with agent-scope (sc1) accesses, which
-// the memory system keeps coherent across the XCDs' L2 caches, so no cache
-// has to be written back or invalidated at the barrier.
-#ifndef L1_TAIL_LOAD_SC1
-#define L1_TAIL_LOAD_SC1 1
-#endif
-#ifndef L1_TAIL_STORE_SC1
-#define L1_TAIL_STORE_SC1 1
-#endif
 __device__ inline unsigned long long ld8c(const void* p) {
   return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline u4 ld16c(const void* p) {
-  if (!L1_TAIL_LOAD_SC1) return *reinterpret_cast<const u4*>(p);
   const unsigned long long a = ld8c(p);
   const unsigned long long b = ld8c(reinterpret_cast<const char*>(p) + 8);
   return u4{(unsigned)a, (unsigned)(a >> 32), (unsigned)b, (unsigned)(b >> 32)};
 }
 __device__ inline float ldfc(const float* p) {
-  if (!L1_TAIL_LOAD_SC1) return *p;
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void stfc(float* p, float v) {
-  if (!L1_TAIL_STORE_SC1) { *p = v; return; }
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void sthc(uint16_t* p, uint16_t v) {
-  if (!L1_TAIL_STORE_SC1) { *p = v; return; }
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -79,16 +69,12 @@ __device__ inline void sthc(uint16_t* p, uint16_t v) {
 __device__ inline int ldu32(int n_pad) { return n_pad + 4; }
 __device__ inline int ldu16(int n_pad) { return n_pad + 8; }
 
-// grid barrier on an uncached counter; false if it gave up
-#ifndef L1_TAIL_FENCE
-#define L1_TAIL_FENCE 0
-#endif
+// grid barrier on a counter in device memory; false if it gave up
 __device__ inline bool tail_sync(unsigned* bar, unsigned target, int* flag) {
   __shared__ int s_ok;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (L1_TAIL_FENCE >= 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     atomicAdd(bar, 1u);
     int ok = 1;
     unsigned spins = 0;
@@ -101,10 +87,9 @@ __device__ inline bool tail_sync(unsigned* bar, unsigned target, int* flag) {
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    if (L1_TAIL_FENCE >= 2) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // drop this compute unit's vector L1 so the next loads of published data
     // (and of this workgroup's own rows) come from memory
-    if (L1_TAIL_FENCE == 0) asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
     s_ok = ok;
   }
   __syncthreads();
