@@ -58,6 +58,20 @@ __device__ inline int decide(const TestParams& tp, int st, const float (&sm)[NPA
   return st;
 }
 
+// decide() for sums that come from a product made in arithmetic `arith`:
+// when that is below the phase st the instance has reached since (it was
+// switched while its tile still ran the lower arithmetic), the sums measure
+// the lower arithmetic's stall and decide nothing but a non-finite value.
+__device__ inline int decide_in(const TestParams& tp, int st, int arith, const float (&sm)[NPART],
+                                int* status) {
+  if (arith >= st) return decide(tp, st, sm, status);
+  if (!(isfinite(sm[0]) && isfinite(sm[1]) && isfinite(fabsf(sm[3])))) {
+    *status = L1_NONFINITE;
+    return NPHASE;
+  }
+  return st;
+}
+
 // Block soft-threshold scale of the eps-ball block of P_{1,2}:
 // prox of (eps/beta)||.||_2 applied to s is s * max(0, 1 - (eps/beta)/||s||).
 __device__ inline float ball_scale(float se, float eps, float beta) {

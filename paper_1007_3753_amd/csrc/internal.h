@@ -131,12 +131,19 @@ struct GemmArgs {
   float* ws;            // null: no split-K
   int ws_slots;         // slot stride of ws (= n_col_tiles * TILE of the launch)
   int n_ctiles;         // column tiles covered by the launch grid
-  // ---- per-instance state (DALM iteration launches; null otherwise).  The
-  // prologue of a launch tests the previous iteration of its 64 columns from
-  // prev_partial, skips finished columns and runs the tile in the highest
-  // phase among its live columns; row tile 0 records the new state.
+  // ---- per-instance state (DALM iteration launches; null otherwise).  A
+  // launch multiplies every listed column of its tile in the arithmetic of
+  // the tile's phase group (slot_col / phase_off, regrouped by compaction),
+  // tests the previous iteration of its columns from prev_partial while the
+  // product runs, and updates only the columns that go on; row tile 0
+  // records the new state.
   const int* state_in;   // phases before this launch (read by every workgroup)
   int* state_out;        // phases after its test (written by row tile 0)
+  // arithmetic (phase) of each column's product in the previous launch and
+  // in this one (written by row tile 0); null: not tracked.  Sums made in a
+  // lower arithmetic than the instance's phase decide nothing.
+  const int* arith_in;
+  int* arith_out;
   int* iters;
   int* status;
   const float* prev_partial;   // null: no test (first iteration of a solve)

@@ -51,12 +51,16 @@ __device__ inline void st16(void* p, u4 v) { *reinterpret_cast<u4*>(p) = v; }
 
 // LDS tiles: 0 = A (hi), 1 = B (hi), 2 = A lo, 3 = B lo; rows of LDSROW bytes
 constexpr int LDSTILE = 64 * LDSROW;
+// row tiles of partial sums per lane loaded before the K loop (the rest after it)
+constexpr int TEST_PRE = 8;
 
 // The K loop of a workgroup is a chain of global-memory round trips; each
 // takes ~1 us under load, far longer than the MFMA work on one slice.  Both
 // main loops keep D slices in flight in registers: slice k + D is requested
 // as soon as slice k has been moved to LDS.  Every load is unconditional (the
-// slice index is clamped, idle columns read column 0 and are masked to zero)
+// slice index is clamped; an empty slot reads column 0, whose products are
+// never stored: each output column depends on its own B column only, so no
+// load result is masked, which would make the compiler wait for it at once)
 // and the steady-state loop runs a multiple of D steps, so the wait inserted
 // before a register set is consumed always leaves the younger D - 1 slices in
 // flight, also across the loop back-edge.  D is a compile-time constant so
@@ -75,7 +79,6 @@ __device__ inline void mainloop_f32(const GemmArgs& a, int i0, const int* colidx
   const bool v0 = bc0 >= 0, v1 = bc1 >= 0;
   const long brow0 = (long)(v0 ? bc0 : 0) * a.ldb * 4;
   const long brow1 = (long)(v1 ? bc1 : 0) * a.ldb * 4;
-  const u4 z4 = {0u, 0u, 0u, 0u};
   // [kb, ke) is given in 64-element units; FP32 slices hold 32 elements
   A += (long)kb * 256;
   B += (long)kb * 256;
@@ -87,10 +90,8 @@ __device__ inline void mainloop_f32(const GemmArgs& a, int i0, const int* colidx
     const long off = (long)min((kt), nk - 1) * 128 + ch * 16; \
     ra[d][0] = ld16(A + arow0 + off);                         \
     ra[d][1] = ld16(A + arow1 + off);                         \
-    const u4 b0 = ld16(B + brow0 + off);                      \
-    const u4 b1 = ld16(B + brow1 + off);                      \
-    rb[d][0] = v0 ? b0 : z4;                                  \
-    rb[d][1] = v1 ? b1 : z4;                                  \
+    rb[d][0] = ld16(B + brow0 + off);                         \
+    rb[d][1] = ld16(B + brow1 + off);                         \
   }
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
@@ -151,7 +152,6 @@ __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colid
   const bool v0 = bc0 >= 0, v1 = bc1 >= 0;
   const long brow0 = (long)(v0 ? bc0 : 0) * a.ldb * 2;
   const long brow1 = (long)(v1 ? bc1 : 0) * a.ldb * 2;
-  const u4 z4 = {0u, 0u, 0u, 0u};
   Ah += (long)kb * 128;
   Bh += (long)kb * 128;
   if (SPLIT) {
@@ -166,17 +166,13 @@ __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colid
     const long off = (long)min((kt), nk - 1) * 128 + ch * 16; \
     rah[d][0] = ld16(Ah + arow0 + off);                       \
     rah[d][1] = ld16(Ah + arow1 + off);                       \
-    const u4 h0 = ld16(Bh + brow0 + off);                     \
-    const u4 h1 = ld16(Bh + brow1 + off);                     \
-    rbh[d][0] = v0 ? h0 : z4;                                 \
-    rbh[d][1] = v1 ? h1 : z4;                                 \
+    rbh[d][0] = ld16(Bh + brow0 + off);                       \
+    rbh[d][1] = ld16(Bh + brow1 + off);                       \
     if (SPLIT) {                                              \
       ral[d][0] = ld16(Al + arow0 + off);                     \
       ral[d][1] = ld16(Al + arow1 + off);                     \
-      const u4 l0 = ld16(Bl + brow0 + off);                   \
-      const u4 l1 = ld16(Bl + brow1 + off);                   \
-      rbl[d][0] = v0 ? l0 : z4;                               \
-      rbl[d][1] = v1 ? l1 : z4;                               \
+      rbl[d][0] = ld16(Bl + brow0 + off);                     \
+      rbl[d][1] = ld16(Bl + brow1 + off);                     \
     }                                                         \
   }
   const int lane = tid & 63, wave = tid >> 6;
@@ -268,69 +264,39 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   if (slot0 >= nslots) return;  // uniform for the workgroup
   const int tid = threadIdx.x;
   __shared__ float s_zsc[64];
-  __shared__ int s_prec, s_live;
+  __shared__ int s_live;
   if (tid < 64) {
     const int sl = slot0 + tid;
     colidx[tid] = (sl < nslots) ? (a.slot_col ? a.slot_col[sl] : sl) : -1;
     s_zsc[tid] = 1.0f;
   }
-  if (tid == 0) {
-    s_prec = -1;
-    s_live = 0;
-  }
+  if (tid == 0) s_live = 0;
   __syncthreads();
-  if (a.state_in) {
-    // convergence test of the previous iteration, 4 lanes per column
-    const int sl = tid >> 2, part = tid & 3;
-    const int col = colidx[sl];
-    const int st0 = (col >= 0) ? a.state_in[col] : NPHASE;
-    const bool live0 = st0 < NPHASE;
-    float sm[NPART];
-    column_sums(a.prev_partial, a.ldp, RT, col, live0 && a.prev_partial, part, sm);
-    int st = st0, stat_new = L1_MAXITER;
-    float zs = 1.0f;
-    if (live0 && a.prev_partial && a.test_kind == 1) {
-      // FISTA inner loop: stop on the relative change of the shrink output
-      const float t = a.tp_tol;
-      if (!(isfinite(sm[0]) && isfinite(sm[1]))) st = NPHASE;
-      else if (t >= 0.0f && sm[0] <= t * t * sm[1]) st = NPHASE;
-    } else if (live0 && a.prev_partial) {
-      TestParams tp;
-      tp.tol = a.tp_tol;
-      tp.sw = a.tp_sw;
-      tp.final_phase = a.tp_final;
+
+  // Convergence test of the previous iteration (4 lanes per column).  Its
+  // loads are issued here and its decision is taken after the product, so
+  // that its memory round trips overlap the K loop: the product does not
+  // depend on it, because every listed column is multiplied (a column that
+  // has just finished is simply not updated) in the arithmetic of its phase
+  // group as of the last compaction.  The partial sums are added in the
+  // order of column_sums.
+  const bool test = EPI != EPI_PARTIAL && a.state_in != nullptr;
+  const int tsl = tid >> 2, tpart = tid & 3;
+  const int tcol = colidx[tsl];
+  const bool tload = test && tcol >= 0 && a.prev_partial != nullptr;
+  int st0 = NPHASE, ar0 = 0;
+  float tv[TEST_PRE][NPART];
+  if (test) {
+    // unconditional loads from clamped addresses (values masked when summed)
+    const float* pp = a.prev_partial ? a.prev_partial : a.partial;
+    const int cc = tcol >= 0 ? tcol : 0;
+    st0 = a.state_in[cc];
+    ar0 = a.arith_in ? a.arith_in[cc] : NPHASE;
 #pragma unroll
-      for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.tp_floor[q];
-      st = decide(tp, st0, sm, &stat_new);
-      if (a.eps) zs = ball_scale(sm[4], a.eps[col], a.beta[col]);
-    } else if (live0 && a.eps) {
-      zs = a.zscale[col];
-    }
-    if (part == 0 && col >= 0) {
-      if (st < NPHASE) {
-        s_zsc[sl] = zs;
-        atomicMax(&s_prec, st);
-        atomicAdd(&s_live, 1);
-      } else {
-        colidx[sl] = -1;
-      }
-      if (EPI != EPI_PARTIAL && rt == 0) {
-        a.state_out[col] = st;
-        if (live0) {
-          if (st >= NPHASE) {
-            if (a.status) a.status[col] = stat_new;
-          } else {
-            a.iters[col] += 1;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    if (s_live == 0) return;  // every column of the tile has finished
-    prec = s_prec;
-    if (EPI != EPI_PARTIAL && rt == 0 && tid == 0 && a.stat) {
-      atomicAdd((unsigned long long*)&a.stat[3 + prec], (unsigned long long)s_live);
-      atomicAdd((unsigned long long*)&a.stat[prec], 1ull);
+    for (int i = 0; i < TEST_PRE; ++i) {
+      const int t = min(tpart + 4 * i, RT - 1);
+#pragma unroll
+      for (int q = 0; q < NPART; ++q) tv[i][q] = pp[(long)(t * NPART + q) * a.ldp + cc];
     }
   }
 
@@ -373,6 +339,85 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
           *reinterpret_cast<f4*>(a.ws + o) = acc[bi][bj];
         }
       return;
+    }
+  }
+
+  if (test) {
+    // the loaded values enter the arithmetic only here: the empty asm keeps
+    // the compiler from starting the sums (and so waiting for the loads)
+    // before the K loop
+    asm volatile("" : "+v"(st0));
+    asm volatile("" : "+v"(ar0));
+#pragma unroll
+    for (int i = 0; i < TEST_PRE; ++i)
+#pragma unroll
+      for (int q = 0; q < NPART; ++q) asm volatile("" : "+v"(tv[i][q]));
+    float sm[NPART];
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) sm[q] = 0.0f;
+    const bool live0 = tcol >= 0 && st0 < NPHASE;
+    if (tload && live0) {
+#pragma unroll
+      for (int i = 0; i < TEST_PRE; ++i)
+        if (tpart + 4 * i < RT) {
+#pragma unroll
+          for (int q = 0; q < NPART; ++q) sm[q] += tv[i][q];
+        }
+      for (int t = tpart + 4 * TEST_PRE; t < RT; t += 4) {
+        const float* pt = a.prev_partial + (long)t * NPART * a.ldp + tcol;
+#pragma unroll
+        for (int q = 0; q < NPART; ++q) sm[q] += pt[(long)q * a.ldp];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) {
+      sm[q] += __shfl_xor(sm[q], 1);
+      sm[q] += __shfl_xor(sm[q], 2);
+    }
+    int st = live0 ? st0 : NPHASE, stat_new = L1_MAXITER;
+    float zs = 1.0f;
+    if (live0 && a.prev_partial && a.test_kind == 1) {
+      // FISTA inner loop: stop on the relative change of the shrink output
+      const float t = a.tp_tol;
+      if (!(isfinite(sm[0]) && isfinite(sm[1]))) st = NPHASE;
+      else if (t >= 0.0f && sm[0] <= t * t * sm[1]) st = NPHASE;
+    } else if (live0 && a.prev_partial) {
+      TestParams tp;
+      tp.tol = a.tp_tol;
+      tp.sw = a.tp_sw;
+      tp.final_phase = a.tp_final;
+#pragma unroll
+      for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.tp_floor[q];
+      st = decide_in(tp, st0, ar0, sm, &stat_new);
+      if (a.eps) zs = ball_scale(sm[4], a.eps[tcol], a.beta[tcol]);
+    } else if (live0 && a.eps) {
+      zs = a.zscale[tcol];
+    }
+    __syncthreads();  // the K loop has read colidx
+    if (tpart == 0 && tcol >= 0) {
+      if (st < NPHASE) {
+        s_zsc[tsl] = zs;
+        atomicAdd(&s_live, 1);
+      } else {
+        colidx[tsl] = -1;
+      }
+      if (rt == 0) {
+        a.state_out[tcol] = st;
+        if (a.arith_out && st < NPHASE) a.arith_out[tcol] = prec;
+        if (live0) {
+          if (st >= NPHASE) {
+            if (a.status) a.status[tcol] = stat_new;
+          } else {
+            a.iters[tcol] += 1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (s_live == 0) return;  // every column of the tile has finished
+    if (rt == 0 && tid == 0 && a.stat) {
+      atomicAdd((unsigned long long*)&a.stat[3 + prec], (unsigned long long)s_live);
+      atomicAdd((unsigned long long*)&a.stat[prec], 1ull);
     }
   }
 

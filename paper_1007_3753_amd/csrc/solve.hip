@@ -179,6 +179,8 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   }
   const Lists L = lists_of(p);
   int* stbuf[2] = {L.state, p->ints + 5 * p->N_pad + 256};
+  // arithmetic of each column's product: iteration k writes arbuf[k & 1]
+  int* arbuf[2] = {p->ints + 6 * p->N_pad + 256, p->ints + 7 * p->N_pad + 256};
   init_lists(s, N, first, L, stbuf[1], p->stat);
 
   // tape: checkpoints of (W, V) every k iterations of a fixed-count solve
@@ -248,6 +250,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   for (int q = 0; q < NPHASE; ++q) ck.floor[q] = floors[q];
   ck.sw = sw;
   ck.final_phase = last;
+  ck.low_cap = 2000;
   ck.L = L;
   ck.eps = eps;
   ck.beta = p->pen;
@@ -301,6 +304,8 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     it.Ulo = p->Ul[1 - cur];
     it.state_in = stbuf[cur];
     it.state_out = stbuf[1 - cur];
+    it.arith_in = arbuf[1 - cur];
+    it.arith_out = arbuf[cur];
     it.prev_partial = (k == 0) ? nullptr : part[1 - cur];
     it.partial = part[cur];
     launch_product(s, EPI_DALM, it, sh.ctiles, sh.ks);
@@ -410,6 +415,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           ta.slot_col = L.slot_col;
           ta.phase_off = L.phase_off;
           ta.reg_partial = part[(done - 1) & 1];
+          ta.reg_arith = arbuf[(done - 1) & 1];
           ta.ldp = p->N_pad;
           ta.ntiles = p->ntiles;
           ta.U32 = p->Uf[done & 1];
@@ -526,6 +532,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     const int klast = done - 1;
     ck.L.state = stbuf[(klast + 1) & 1];
     ck.partial = part[klast & 1];
+    ck.arith = arbuf[klast & 1];
     dalm_final_test(s, ck);
   }
   L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));

@@ -34,11 +34,14 @@ struct DalmInit {
 struct DalmCheck {
   int N;
   const float* partial;  // partial sums of the iteration to test (final test)
+  const int* arith;      // arithmetic of that iteration's products (null: not tracked)
   int ldp, ntiles;
   float tol;             // < 0: never converge (fixed iteration count)
   float floor[NPHASE];   // the final test uses max(tol, floor[phase])
   float sw;              // exit threshold of a non-final phase
   int final_phase;
+  int low_cap;           // > 0: compaction moves an instance out of a non-final
+                         // phase once it has run this many iterations
   Lists L;               // L.state: the current phase buffer
   int* state_other;      // the other phase buffer (compaction copies into it)
   const float* eps;      // P_{1,2} radii

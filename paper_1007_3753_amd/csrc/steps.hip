@@ -143,7 +143,15 @@ __global__ __launch_bounds__(1024) void dalm_compact_kernel(DalmCheck a) {
   __syncthreads();
   int my[NPHASE] = {0, 0, 0}, mymax = 0;
   for (int c = threadIdx.x; c < a.N; c += 1024) {
-    const int st = a.L.state[c];
+    int st = a.L.state[c];
+    // an instance whose low-precision iteration stalls above the switch
+    // threshold would never leave its phase: after low_cap iterations it
+    // moves on (its next test then sees sums of the old arithmetic and
+    // decides nothing)
+    if (st < NPHASE && st != a.final_phase && a.low_cap > 0 && a.L.iters[c] >= a.low_cap) {
+      st += 1;
+      a.L.state[c] = st;
+    }
     a.state_other[c] = st;
     if (st < NPHASE) my[st] += 1;
     mymax = max(mymax, a.L.iters[c]);
@@ -193,7 +201,7 @@ __global__ __launch_bounds__(256) void dalm_final_test_kernel(DalmCheck a) {
   tp.final_phase = a.final_phase;
   for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.floor[q];
   int status = L1_MAXITER;
-  const int st = decide(tp, st0, sm, &status);
+  const int st = decide_in(tp, st0, a.arith ? a.arith[c] : NPHASE, sm, &status);
   if (st != st0) a.L.state[c] = st;
   if (st >= NPHASE) a.L.status[c] = status;
 }

@@ -33,6 +33,7 @@ struct TailArgs {
   // the iteration before the tail: its partial sums (tile layout) and the
   // B operand it produced
   const float* reg_partial;
+  const int* reg_arith;         // arithmetic of that iteration's products
   int ldp, ntiles;
   const float* U32;
   const uint16_t* Uhi;

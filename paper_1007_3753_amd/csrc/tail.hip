@@ -262,7 +262,10 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
           sm[p] = v;
         }
         int stat_new = L1_MAXITER;
-        const int st = decide(a.tp, s_st[j], sm, &stat_new);
+        // the first sums come from the launch-per-iteration path, whose
+        // product may have run in a lower arithmetic than the final phase
+        const int ar = (first && a.reg_arith) ? a.reg_arith[s_col[j]] : NPHASE;
+        const int st = decide_in(a.tp, s_st[j], ar, sm, &stat_new);
         if (g == 0) {
           if (st >= NPHASE) a.status[s_col[j]] = stat_new;
           else if (k < a.k_end) a.iters[s_col[j]] += 1;
