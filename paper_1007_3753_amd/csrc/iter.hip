@@ -39,7 +39,11 @@ __device__ inline uint16_t f2bf(float f) {
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 constexpr int ROWB = 128;        // bytes of one K slice per row
-constexpr int LDSROW = ROWB + 16;  // padded LDS row (bank spread for 16-byte reads)
+// LDS byte offset of 16-byte chunk c of tile row r.  Rows are unpadded and the
+// chunk index is XORed with bits 1..3 of the row, so that the 16 lanes of a
+// fragment read (rows r..r+15, one chunk) and the 16 lanes of a staging write
+// (two rows, eight chunks) each touch 16 distinct 16-byte bank groups.
+__device__ inline int lo(int r, int c) { return r * ROWB + ((c ^ ((r >> 1) & 7)) << 4); }
 
 __device__ inline float clamp1(float x) { return fminf(fmaxf(x, -1.0f), 1.0f); }
 __device__ inline float softf(float x, float a) {
@@ -49,8 +53,8 @@ __device__ inline float softf(float x, float a) {
 __device__ inline u4 ld16(const void* p) { return *reinterpret_cast<const u4*>(p); }
 __device__ inline void st16(void* p, u4 v) { *reinterpret_cast<u4*>(p) = v; }
 
-// LDS tiles: 0 = A (hi), 1 = B (hi), 2 = A lo, 3 = B lo; rows of LDSROW bytes
-constexpr int LDSTILE = 64 * LDSROW;
+// LDS tiles: 0 = A (hi), 1 = B (hi), 2 = A lo, 3 = B lo; 64 rows of ROWB bytes
+constexpr int LDSTILE = 64 * ROWB;
 // row tiles of partial sums per lane loaded before the K loop (the rest after it)
 constexpr int TEST_PRE = 8;
 
@@ -97,18 +101,17 @@ __device__ inline void mainloop_f32(const GemmArgs& a, int i0, const int* colidx
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
 #define L1_STEP_F32(d, kt_next)                                                              \
   {                                                                                          \
-    st16(&lds[rr * LDSROW + ch * 16], ra[d][0]);                                             \
-    st16(&lds[(rr + 32) * LDSROW + ch * 16], ra[d][1]);                                      \
-    st16(&lds[LDSTILE + rr * LDSROW + ch * 16], rb[d][0]);                                   \
-    st16(&lds[LDSTILE + (rr + 32) * LDSROW + ch * 16], rb[d][1]);                            \
+    st16(&lds[lo(rr, ch)], ra[d][0]);                                             \
+    st16(&lds[lo(rr + 32, ch)], ra[d][1]);                                      \
+    st16(&lds[LDSTILE + lo(rr, ch)], rb[d][0]);                                   \
+    st16(&lds[LDSTILE + lo(rr + 32, ch)], rb[d][1]);                            \
     __syncthreads();                                                                         \
     L1_FETCH_F32(d, kt_next)                                                                 \
     _Pragma("unroll") for (int kc = 0; kc < 2; ++kc) {                                       \
-      const int boff = kc * 64 + q * 16;                                                     \
       u4 fa[2], fb[2];                                                                       \
       _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                        \
-        fa[i] = ld16(&lds[(wm * 32 + i * 16 + li) * LDSROW + boff]);                         \
-        fb[i] = ld16(&lds[LDSTILE + (wn * 32 + i * 16 + li) * LDSROW + boff]);               \
+        fa[i] = ld16(&lds[lo(wm * 32 + i * 16 + li, kc * 4 + q)]);                         \
+        fb[i] = ld16(&lds[LDSTILE + lo(wn * 32 + i * 16 + li, kc * 4 + q)]);               \
       }                                                                                      \
       /* lane (li, q) holds k = 4q..4q+3 of this 16-wide chunk; MFMA step s takes  */        \
       /* element s from every lane, so the four steps cover the chunk             */        \
@@ -179,24 +182,23 @@ __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colid
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
 #define L1_STEP_BF(d, kt_next)                                                                \
   {                                                                                           \
-    st16(&lds[rr * LDSROW + ch * 16], rah[d][0]);                                             \
-    st16(&lds[(rr + 32) * LDSROW + ch * 16], rah[d][1]);                                      \
-    st16(&lds[LDSTILE + rr * LDSROW + ch * 16], rbh[d][0]);                                   \
-    st16(&lds[LDSTILE + (rr + 32) * LDSROW + ch * 16], rbh[d][1]);                            \
+    st16(&lds[lo(rr, ch)], rah[d][0]);                                             \
+    st16(&lds[lo(rr + 32, ch)], rah[d][1]);                                      \
+    st16(&lds[LDSTILE + lo(rr, ch)], rbh[d][0]);                                   \
+    st16(&lds[LDSTILE + lo(rr + 32, ch)], rbh[d][1]);                            \
     if (SPLIT) {                                                                              \
-      st16(&lds[2 * LDSTILE + rr * LDSROW + ch * 16], ral[d][0]);                             \
-      st16(&lds[2 * LDSTILE + (rr + 32) * LDSROW + ch * 16], ral[d][1]);                      \
-      st16(&lds[3 * LDSTILE + rr * LDSROW + ch * 16], rbl[d][0]);                             \
-      st16(&lds[3 * LDSTILE + (rr + 32) * LDSROW + ch * 16], rbl[d][1]);                      \
+      st16(&lds[2 * LDSTILE + lo(rr, ch)], ral[d][0]);                             \
+      st16(&lds[2 * LDSTILE + lo(rr + 32, ch)], ral[d][1]);                      \
+      st16(&lds[3 * LDSTILE + lo(rr, ch)], rbl[d][0]);                             \
+      st16(&lds[3 * LDSTILE + lo(rr + 32, ch)], rbl[d][1]);                      \
     }                                                                                         \
     __syncthreads();                                                                          \
     L1_FETCH_BF(d, kt_next)                                                                   \
     _Pragma("unroll") for (int kc = 0; kc < 2; ++kc) {                                        \
-      const int boff = kc * 64 + q * 16;                                                      \
       bf8 ah[2], bh[2], al[2], bl[2];                                                         \
       _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                         \
-        const int ar = (wm * 32 + i * 16 + li) * LDSROW + boff;                               \
-        const int br = LDSTILE + (wn * 32 + i * 16 + li) * LDSROW + boff;                     \
+        const int ar = lo(wm * 32 + i * 16 + li, kc * 4 + q);                               \
+        const int br = LDSTILE + lo(wn * 32 + i * 16 + li, kc * 4 + q);                     \
         ah[i] = __builtin_bit_cast(bf8, ld16(&lds[ar]));                                      \
         bh[i] = __builtin_bit_cast(bf8, ld16(&lds[br]));                                      \
         if (SPLIT) {                                                                          \
@@ -492,8 +494,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
           if (ball) part[bj][4] += s2 * s2;
         }
         *reinterpret_cast<f4*>(a.V + idx) = vn4;
-        *reinterpret_cast<f4*>(a.U + idx) = un4;
-        if (a.Uhi) {
+        // the next product reads u in the tile's arithmetic family (a phase
+        // group never moves between the BF16 forms and FP32)
+        if (prec == PREC_F32 || !a.Uhi) *reinterpret_cast<f4*>(a.U + idx) = un4;
+        if (a.Uhi && prec != PREC_F32) {
           us4 h, l;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
