@@ -269,7 +269,7 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   p->ints = dalloc<int>(Np * 8 + 512, o);
   p->stat = dalloc<long long>(8, o);
   p->kkt_rbuf = dalloc<double>((size_t)m * Np, o);
-  L1_HIP(hipHostMalloc((void**)&p->h_total, sizeof(int) * 4, 0));
+  L1_HIP(hipHostMalloc((void**)&p->h_total, sizeof(int) * 8, 0));
   L1_HIP(hipStreamSynchronize(s));
   return p.release();
 }

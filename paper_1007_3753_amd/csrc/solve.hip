@@ -273,10 +273,14 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   // iterations (graph replay or uncaptured launches; the block's compaction
   // included), so the timed launches run exactly as untimed ones do
   const bool timing = p->d.time_kernels != 0;
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev;     // ev[0..1]: the tail launch; tev: the blocks, two slots
+  hipEvent_t* tev = nullptr;
+  hipEvent_t cev[2] = {nullptr, nullptr};  // the blocks' count copies
+  for (auto& e : cev) L1_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   if (timing) {
-    ev.resize(2);
+    ev.resize(6);
     for (auto& e : ev) L1_HIP(hipEventCreate(&e));
+    tev = ev.data() + 2;
   }
   // Launch shape of a block of iterations, from the number of unfinished
   // instances polled before it (the count only shrinks inside a block):
@@ -367,6 +371,11 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     graphs.clear();
     for (auto e : ev) (void)hipEventDestroy(e);
     ev.clear();
+    for (auto& e : cev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
   };
 
   long long hstat[8] = {0};
@@ -382,11 +391,32 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   if (const char* e = std::getenv("L1ALM_TAIL")) tail_ok = tail_ok && e[0] != '0';
   bool tail_done = false;
   int tail_retry = 0;
+  // The host keeps one block of iterations queued ahead of the block whose
+  // unfinished-instance count it reads: the shape of a block comes from the
+  // count after the block before the previous one.  The count never grows,
+  // so a stale count still covers every unfinished instance (and a tail
+  // launch chosen from it has room for all of them); at worst one block too
+  // many is launched, whose launches find no listed instance.
+  int* hcnt = p->h_total + 4;   // two pinned count slots
+  int pend = -1, pend_blk = 0, nslot = 0;
+  auto retire = [&]() {
+    if (pend < 0) return;
+    L1_HIP(hipEventSynchronize(cev[pend]));
+    active = hcnt[pend];
+    if (timing) {
+      float ms = 0.0f;
+      L1_HIP(hipEventElapsedTime(&ms, tev[2 * pend], tev[2 * pend + 1]));
+      timed_ms += ms;
+      timed_n += pend_blk;
+    }
+    pend = -1;
+  };
   try {
     while (done < cap) {
       const int blk = std::min(BLK, cap - done);
-      const Shape sh = shape_for(active);
+      const Shape sh = shape_for(std::max(active, 1));
       if (tail_ok && done > 0 && done >= tail_retry && active <= tail_cap) {
+        retire();
         const int G = p->n_pad / TAIL_ROWS;
         const size_t xu = tail_f32 ? (size_t)TAIL_NC * p->n_pad * 4 : (size_t)TAIL_NC * p->n_pad * 2;
         const size_t xp = (size_t)G * NPART * TAIL_NC * 4;
@@ -474,7 +504,6 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
             tail_done = true;
             compact_after(done - 1);
             L1_HIP(hipMemcpyAsync(p->h_total, L.n_total, sizeof(int), hipMemcpyDeviceToHost, s));
-            L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
             L1_HIP(hipStreamSynchronize(s));
             active = *p->h_total;
             break;
@@ -489,7 +518,9 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
         gx = graph_for(sh);
         if (!gx) graphs_ok = false;
       }
-      if (timing) L1_HIP(hipEventRecord(ev[0], s));
+      const int slot = nslot;
+      nslot ^= 1;
+      if (timing) L1_HIP(hipEventRecord(tev[2 * slot], s));
       if (gx) {
         L1_HIP(hipGraphLaunch(gx, s));
       } else {
@@ -506,21 +537,16 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
         }
         compact_after(done + blk - 1);
       }
-      if (timing) L1_HIP(hipEventRecord(ev[1], s));
+      if (timing) L1_HIP(hipEventRecord(tev[2 * slot + 1], s));
       done += blk;
-      L1_HIP(hipMemcpyAsync(p->h_total, L.n_total, sizeof(int), hipMemcpyDeviceToHost, s));
-      L1_HIP(hipMemcpyAsync(hstat, p->stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
-      L1_HIP(hipStreamSynchronize(s));
-      active = *p->h_total;
-      if (timing) {
-        float ms = 0.0f;
-        L1_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        timed_ms += ms;
-        timed_n += blk;
-      }
+      L1_HIP(hipMemcpyAsync(hcnt + slot, L.n_total, sizeof(int), hipMemcpyDeviceToHost, s));
+      L1_HIP(hipEventRecord(cev[slot], s));
+      retire();  // the block before this one (this one keeps the device busy)
+      pend = slot;
+      pend_blk = blk;
       if (!fixed && active == 0) break;
-      if (active == 0) active = 1;
     }
+    retire();
   } catch (...) {
     release();
     throw;
