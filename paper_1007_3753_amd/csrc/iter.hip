@@ -53,22 +53,29 @@ __device__ inline float softf(float x, float a) {
 __device__ inline u4 ld16(const void* p) { return *reinterpret_cast<const u4*>(p); }
 __device__ inline void st16(void* p, u4 v) { *reinterpret_cast<u4*>(p) = v; }
 
-// LDS tiles: 0 = A (hi), 1 = B (hi), 2 = A lo, 3 = B lo; 64 rows of ROWB bytes
+// LDS tiles of one stage buffer: 0 = A (hi), 1 = B (hi), 2 = A lo, 3 = B lo;
+// 64 rows of ROWB bytes each; two stage buffers
 constexpr int LDSTILE = 64 * ROWB;
+constexpr int STAGE = 4 * LDSTILE;
+constexpr int GEMM_LDS = 2 * STAGE;
 // row tiles of partial sums per lane loaded before the K loop (the rest after it)
 constexpr int TEST_PRE = 8;
 
 // The K loop of a workgroup is a chain of global-memory round trips; each
 // takes ~1 us under load, far longer than the MFMA work on one slice.  Both
-// main loops keep D slices in flight in registers: slice k + D is requested
-// as soon as slice k has been moved to LDS.  Every load is unconditional (the
-// slice index is clamped; an empty slot reads column 0, whose products are
-// never stored: each output column depends on its own B column only, so no
-// load result is masked, which would make the compiler wait for it at once)
-// and the steady-state loop runs a multiple of D steps, so the wait inserted
-// before a register set is consumed always leaves the younger D - 1 slices in
-// flight, also across the loop back-edge.  D is a compile-time constant so
-// every register set is statically indexed.
+// main loops keep D slices in flight in registers and stage slices through
+// two LDS buffers: in step k the workgroup multiplies slice k from buffer
+// k & 1 while it moves slice k + 1 from registers into the other buffer and
+// requests slice k + 1 + D into the registers just freed, so one barrier per
+// step (at its start) both publishes slice k and frees the buffer written
+// next.  Every load is unconditional (the slice index is clamped; an empty
+// slot reads column 0, whose products are never stored: each output column
+// depends on its own B column only, so no load result is masked, which would
+// make the compiler wait for it at once) and the steady-state loop runs a
+// multiple of D steps, so the wait inserted before a register set is
+// consumed always leaves the younger D - 1 slices in flight, also across the
+// loop back-edge.  D is a compile-time constant so every register set is
+// statically indexed.
 
 // ---- FP32 main loop: 32-element K slices, v_mfma_f32_16x16x4_f32 ----------
 template <int D>
@@ -80,9 +87,8 @@ __device__ inline void mainloop_f32(const GemmArgs& a, int i0, const int* colidx
   const char* B = reinterpret_cast<const char*>(a.B);
   const long arow0 = (long)(i0 + rr) * a.lda * 4, arow1 = (long)(i0 + rr + 32) * a.lda * 4;
   const int bc0 = colidx[rr], bc1 = colidx[rr + 32];
-  const bool v0 = bc0 >= 0, v1 = bc1 >= 0;
-  const long brow0 = (long)(v0 ? bc0 : 0) * a.ldb * 4;
-  const long brow1 = (long)(v1 ? bc1 : 0) * a.ldb * 4;
+  const long brow0 = (long)(bc0 >= 0 ? bc0 : 0) * a.ldb * 4;
+  const long brow1 = (long)(bc1 >= 0 ? bc1 : 0) * a.ldb * 4;
   // [kb, ke) is given in 64-element units; FP32 slices hold 32 elements
   A += (long)kb * 256;
   B += (long)kb * 256;
@@ -97,21 +103,28 @@ __device__ inline void mainloop_f32(const GemmArgs& a, int i0, const int* colidx
     rb[d][0] = ld16(B + brow0 + off);                         \
     rb[d][1] = ld16(B + brow1 + off);                         \
   }
+#define L1_PUT_F32(d, buf)                                             \
+  {                                                                    \
+    unsigned char* st_ = lds + (buf) * STAGE;                          \
+    st16(&st_[lo(rr, ch)], ra[d][0]);                                  \
+    st16(&st_[lo(rr + 32, ch)], ra[d][1]);                             \
+    st16(&st_[LDSTILE + lo(rr, ch)], rb[d][0]);                        \
+    st16(&st_[LDSTILE + lo(rr + 32, ch)], rb[d][1]);                   \
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
-#define L1_STEP_F32(d, kt_next)                                                              \
+  // step k: slice k + 1 sits in register set (k + 1) % D = dn
+#define L1_STEP_F32(k, dn)                                                                   \
   {                                                                                          \
-    st16(&lds[lo(rr, ch)], ra[d][0]);                                             \
-    st16(&lds[lo(rr + 32, ch)], ra[d][1]);                                      \
-    st16(&lds[LDSTILE + lo(rr, ch)], rb[d][0]);                                   \
-    st16(&lds[LDSTILE + lo(rr + 32, ch)], rb[d][1]);                            \
     __syncthreads();                                                                         \
-    L1_FETCH_F32(d, kt_next)                                                                 \
+    L1_PUT_F32(dn, ((k) + 1) & 1)                                                            \
+    L1_FETCH_F32(dn, (k) + 1 + D)                                                            \
+    const unsigned char* cur_ = lds + ((k) & 1) * STAGE;                                     \
     _Pragma("unroll") for (int kc = 0; kc < 2; ++kc) {                                       \
       u4 fa[2], fb[2];                                                                       \
       _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                        \
-        fa[i] = ld16(&lds[lo(wm * 32 + i * 16 + li, kc * 4 + q)]);                         \
-        fb[i] = ld16(&lds[LDSTILE + lo(wn * 32 + i * 16 + li, kc * 4 + q)]);               \
+        fa[i] = ld16(&cur_[lo(wm * 32 + i * 16 + li, kc * 4 + q)]);                          \
+        fb[i] = ld16(&cur_[LDSTILE + lo(wn * 32 + i * 16 + li, kc * 4 + q)]);                \
       }                                                                                      \
       /* lane (li, q) holds k = 4q..4q+3 of this 16-wide chunk; MFMA step s takes  */        \
       /* element s from every lane, so the four steps cover the chunk             */        \
@@ -121,20 +134,22 @@ __device__ inline void mainloop_f32(const GemmArgs& a, int i0, const int* colidx
         acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(                                  \
             __uint_as_float(fa[bi][s]), __uint_as_float(fb[bj][s]), acc[bi][bj], 0, 0, 0);   \
     }                                                                                        \
-    __syncthreads();                                                                         \
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) L1_FETCH_F32(d, d)
+  L1_PUT_F32(0, 0)
+  L1_FETCH_F32(0, D)
   const int nmain = nk - nk % D;
   for (int k0 = 0; k0 < nmain; k0 += D) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) L1_STEP_F32(d, k0 + d + D)
+    for (int d = 0; d < D; ++d) L1_STEP_F32(k0 + d, (d + 1) % D)
   }
-  // remainder: slices nmain + d already sit in register set d
 #pragma unroll
   for (int d = 0; d < D - 1; ++d)
-    if (nmain + d < nk) L1_STEP_F32(d, nk - 1)
+    if (nmain + d < nk) L1_STEP_F32(nmain + d, (d + 1) % D)
+  __syncthreads();  // the stage is free again
 #undef L1_STEP_F32
+#undef L1_PUT_F32
 #undef L1_FETCH_F32
 }
 
@@ -152,9 +167,8 @@ __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colid
   const char* Bl = reinterpret_cast<const char*>(a.Blo);
   const long arow0 = (long)(i0 + rr) * a.lda * 2, arow1 = (long)(i0 + rr + 32) * a.lda * 2;
   const int bc0 = colidx[rr], bc1 = colidx[rr + 32];
-  const bool v0 = bc0 >= 0, v1 = bc1 >= 0;
-  const long brow0 = (long)(v0 ? bc0 : 0) * a.ldb * 2;
-  const long brow1 = (long)(v1 ? bc1 : 0) * a.ldb * 2;
+  const long brow0 = (long)(bc0 >= 0 ? bc0 : 0) * a.ldb * 2;
+  const long brow1 = (long)(bc1 >= 0 ? bc1 : 0) * a.ldb * 2;
   Ah += (long)kb * 128;
   Bh += (long)kb * 128;
   if (SPLIT) {
@@ -178,32 +192,38 @@ __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colid
       rbl[d][1] = ld16(Bl + brow1 + off);                     \
     }                                                         \
   }
+#define L1_PUT_BF(d, buf)                                              \
+  {                                                                    \
+    unsigned char* st_ = lds + (buf) * STAGE;                          \
+    st16(&st_[lo(rr, ch)], rah[d][0]);                                 \
+    st16(&st_[lo(rr + 32, ch)], rah[d][1]);                            \
+    st16(&st_[LDSTILE + lo(rr, ch)], rbh[d][0]);                       \
+    st16(&st_[LDSTILE + lo(rr + 32, ch)], rbh[d][1]);                  \
+    if (SPLIT) {                                                       \
+      st16(&st_[2 * LDSTILE + lo(rr, ch)], ral[d][0]);                 \
+      st16(&st_[2 * LDSTILE + lo(rr + 32, ch)], ral[d][1]);            \
+      st16(&st_[3 * LDSTILE + lo(rr, ch)], rbl[d][0]);                 \
+      st16(&st_[3 * LDSTILE + lo(rr + 32, ch)], rbl[d][1]);            \
+    }                                                                  \
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
-#define L1_STEP_BF(d, kt_next)                                                                \
+#define L1_STEP_BF(k, dn)                                                                     \
   {                                                                                           \
-    st16(&lds[lo(rr, ch)], rah[d][0]);                                             \
-    st16(&lds[lo(rr + 32, ch)], rah[d][1]);                                      \
-    st16(&lds[LDSTILE + lo(rr, ch)], rbh[d][0]);                                   \
-    st16(&lds[LDSTILE + lo(rr + 32, ch)], rbh[d][1]);                            \
-    if (SPLIT) {                                                                              \
-      st16(&lds[2 * LDSTILE + lo(rr, ch)], ral[d][0]);                             \
-      st16(&lds[2 * LDSTILE + lo(rr + 32, ch)], ral[d][1]);                      \
-      st16(&lds[3 * LDSTILE + lo(rr, ch)], rbl[d][0]);                             \
-      st16(&lds[3 * LDSTILE + lo(rr + 32, ch)], rbl[d][1]);                      \
-    }                                                                                         \
     __syncthreads();                                                                          \
-    L1_FETCH_BF(d, kt_next)                                                                   \
+    L1_PUT_BF(dn, ((k) + 1) & 1)                                                              \
+    L1_FETCH_BF(dn, (k) + 1 + D)                                                              \
+    const unsigned char* cur_ = lds + ((k) & 1) * STAGE;                                      \
     _Pragma("unroll") for (int kc = 0; kc < 2; ++kc) {                                        \
       bf8 ah[2], bh[2], al[2], bl[2];                                                         \
       _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                         \
-        const int ar = lo(wm * 32 + i * 16 + li, kc * 4 + q);                               \
-        const int br = LDSTILE + lo(wn * 32 + i * 16 + li, kc * 4 + q);                     \
-        ah[i] = __builtin_bit_cast(bf8, ld16(&lds[ar]));                                      \
-        bh[i] = __builtin_bit_cast(bf8, ld16(&lds[br]));                                      \
+        const int ar = lo(wm * 32 + i * 16 + li, kc * 4 + q);                                 \
+        const int br = LDSTILE + lo(wn * 32 + i * 16 + li, kc * 4 + q);                       \
+        ah[i] = __builtin_bit_cast(bf8, ld16(&cur_[ar]));                                     \
+        bh[i] = __builtin_bit_cast(bf8, ld16(&cur_[br]));                                     \
         if (SPLIT) {                                                                          \
-          al[i] = __builtin_bit_cast(bf8, ld16(&lds[2 * LDSTILE + ar]));                      \
-          bl[i] = __builtin_bit_cast(bf8, ld16(&lds[2 * LDSTILE + br]));                      \
+          al[i] = __builtin_bit_cast(bf8, ld16(&cur_[2 * LDSTILE + ar]));                     \
+          bl[i] = __builtin_bit_cast(bf8, ld16(&cur_[2 * LDSTILE + br]));                     \
         }                                                                                     \
       }                                                                                       \
       /* four independent accumulators, issued round by round; small terms first */          \
@@ -219,25 +239,28 @@ __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colid
       _Pragma("unroll") for (int bj = 0; bj < 2; ++bj)                                        \
         acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0); \
     }                                                                                         \
-    __syncthreads();                                                                          \
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) L1_FETCH_BF(d, d)
+  L1_PUT_BF(0, 0)
+  L1_FETCH_BF(0, D)
   const int nmain = nk - nk % D;
   for (int k0 = 0; k0 < nmain; k0 += D) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) L1_STEP_BF(d, k0 + d + D)
+    for (int d = 0; d < D; ++d) L1_STEP_BF(k0 + d, (d + 1) % D)
   }
 #pragma unroll
   for (int d = 0; d < D - 1; ++d)
-    if (nmain + d < nk) L1_STEP_BF(d, nk - 1)
+    if (nmain + d < nk) L1_STEP_BF(nmain + d, (d + 1) % D)
+  __syncthreads();  // the stage is free again
 #undef L1_STEP_BF
+#undef L1_PUT_BF
 #undef L1_FETCH_BF
 }
 
 template <int EPI>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[4 * LDSTILE];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];   // GEMM_LDS bytes
   __shared__ int colidx[64];
   __shared__ float red[2][64][NPART];
 
@@ -575,10 +598,22 @@ void launch_gemm(hipStream_t s, int epi, const GemmArgs& a0, int n_col_tiles) {
   const int RT = a.M / 64;
   const int per_xcd = (RT + 7) / 8;
   const unsigned grid = 8u * per_xcd * n_col_tiles * ks;
-  if (epi == EPI_STORE) gemm_kernel<EPI_STORE><<<grid, 256, 0, s>>>(a);
-  else if (epi == EPI_DALM) gemm_kernel<EPI_DALM><<<grid, 256, 0, s>>>(a);
-  else if (epi == EPI_FISTA) gemm_kernel<EPI_FISTA><<<grid, 256, 0, s>>>(a);
-  else gemm_kernel<EPI_PARTIAL><<<grid, 256, 0, s>>>(a);
+  // the two stage buffers exceed the default dynamic LDS limit: raise it once
+  static const bool lds_ok = [] {
+    bool ok = true;
+    for (const void* f : {reinterpret_cast<const void*>(gemm_kernel<EPI_STORE>),
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_DALM>),
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_FISTA>),
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_PARTIAL>)})
+      ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LDS) ==
+                     hipSuccess;
+    return ok;
+  }();
+  L1_REQUIRE(lds_ok, "cannot give the iteration GEMM its LDS stages");
+  if (epi == EPI_STORE) gemm_kernel<EPI_STORE><<<grid, 256, GEMM_LDS, s>>>(a);
+  else if (epi == EPI_DALM) gemm_kernel<EPI_DALM><<<grid, 256, GEMM_LDS, s>>>(a);
+  else if (epi == EPI_FISTA) gemm_kernel<EPI_FISTA><<<grid, 256, GEMM_LDS, s>>>(a);
+  else gemm_kernel<EPI_PARTIAL><<<grid, 256, GEMM_LDS, s>>>(a);
   L1_HIP(hipGetLastError());
 }
 

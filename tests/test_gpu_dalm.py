@@ -174,3 +174,21 @@ def test_p12_dalm_matches_oracle():
                   max_iter=-7)
     o5 = oracle_dalm(A, b, problem="p12", eps=eps, fixed_iters=7)
     assert _rel(np.vstack([_np(r5.x), _np(r5.e)]), o5.w) < 5e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_tail_kernel_reproduces_launch_path(precision, monkeypatch):
+    # at most 6 instances: after the first block the tail kernel runs the rest
+    # of the solve; with it switched off the same iterations run one launch
+    # each.  Same K split and summation order: the same bits.
+    P = cab_problem(m=130, classes=7, per_class=7, N=4, cfg=207)
+    pl = _plan(P.A, structure="cab", precision=precision, max_batch=4)
+    b = torch.as_tensor(P.b, device="cuda")
+    fixed_tail = pl.solve(b, max_iter=-200)
+    tol_tail = pl.solve(b, tol=5e-6, max_iter=20000)
+    monkeypatch.setenv("L1ALM_TAIL", "0")
+    fixed_loop = pl.solve(b, max_iter=-200)
+    tol_loop = pl.solve(b, tol=5e-6, max_iter=20000)
+    assert torch.equal(fixed_tail.x, fixed_loop.x) and torch.equal(fixed_tail.e, fixed_loop.e)
+    assert torch.equal(tol_tail.x, tol_loop.x)
+    assert torch.equal(tol_tail.iters, tol_loop.iters) and torch.equal(tol_tail.status, tol_loop.status)
