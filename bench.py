@@ -142,15 +142,15 @@ def main():
     # algorithmic bytes of one launch: the operator read once, in the element
     # size of the arithmetic (weighted by the instances each arithmetic
     # served), plus per instance the operand u read in that arithmetic
-    # (FP32 4 B, BF16 2 B, split 4 B), v, w, c read and v, w, u written (FP32)
-    # and the BF16 split of u written (4 B) when a BF16 mode runs
+    # (FP32 4 B, BF16 2 B, split 4 B), v, w, c read, v, w written and the next
+    # u written in the arithmetic of its next product (FP32, or the BF16
+    # hi / lo split: 4 B either way)
     esize = {"fp32": 4, "bf16": 2, "split": 4}
     tot_cols = max(sum(cols.values()), 1.0)
     # the operator is read once by every launch that had work (one per
     # iteration of the slowest instance)
     op_bytes = agg["iterations"] * n_full * n_full * sum(esize[k] * cols[k] for k in cols) / tot_cols
-    low = args.precision != "fp32"
-    bytes_total = op_bytes + n_full * sum(cols[k] * (esize[k] + 24 + (4 if low else 0)) for k in cols)
+    bytes_total = op_bytes + n_full * sum(cols[k] * (esize[k] + 24) for k in cols)
     t_mfma = sum(flops[k] / (PEAK_TFLOPS[k] * 1e12) for k in flops)
     t_hbm = bytes_total / (PEAK_HBM_GBS * 1e9)
     tot_flops = sum(flops.values())
