@@ -418,7 +418,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
       if (tail_ok && done > 0 && done >= tail_retry && active <= tail_cap) {
         retire();
         const int G = p->n_pad / TAIL_ROWS;
-        const size_t xu = tail_f32 ? (size_t)TAIL_NC * p->n_pad * 4 : (size_t)TAIL_NC * p->n_pad * 2;
+        const size_t xu = (size_t)TAIL_NC * p->n_pad * 2;
         const size_t xp = (size_t)G * NPART * TAIL_NC * 4;
         const size_t need = 256 + 4 * xu + 2 * xp + 1024;
         unsigned char* pool = reinterpret_cast<unsigned char*>(tail_pool(need));
@@ -457,17 +457,10 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           for (int q = 0; q < NPHASE; ++q) ta.tp.floor[q] = floors[q];
           unsigned char* c = pool + 256;
           for (int b = 0; b < 2; ++b) {
-            if (tail_f32) {
-              ta.xu32[b] = reinterpret_cast<float*>(c);
-              c += xu;
-            } else {
-              ta.xuh[b] = reinterpret_cast<uint16_t*>(c);
-              c += xu;
-              ta.xul[b] = reinterpret_cast<uint16_t*>(c);
-              c += xu;
-            }
+            if (tail_f32) ta.xu32[b] = reinterpret_cast<float*>(c);
+            else ta.xpk[b] = reinterpret_cast<uint32_t*>(c);
+            c += 2 * xu;   // [TAIL_NC][n_pad] words of 4 bytes
           }
-          if (tail_f32) c += 2 * xu;
           for (int b = 0; b < 2; ++b) {
             ta.xpart[b] = reinterpret_cast<float*>(c);
             c += xp;

@@ -40,11 +40,12 @@ struct TailArgs {
   const uint16_t* Ulo;
   TestParams tp;
   // exchange buffers in uncached device memory: the next B operand of the
-  // listed instances ([TAIL_NC][n_pad] each) and the per-workgroup partial
-  // sums ([G][NPART][TAIL_NC]), both double-buffered by iteration parity
+  // listed instances ([TAIL_NC][n_pad] each: FP32, or the BF16 hi and lo
+  // halves packed into one 32-bit word, hi in the low half) and the
+  // per-workgroup partial sums ([G][NPART][TAIL_NC]), both double-buffered by
+  // iteration parity
   float* xu32[2];
-  uint16_t* xuh[2];
-  uint16_t* xul[2];
+  uint32_t* xpk[2];
   float* xpart[2];
   unsigned* bar;                // barrier counter (uncached, zero at launch)
   int* flag;                    // [0] barrier gave up, [1] iterations done

@@ -59,9 +59,6 @@ __device__ inline float ldfc(const float* p) {
 __device__ inline void stfc(float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void sthc(uint16_t* p, uint16_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // staged u: column j of the f32 stage at j * ldu32 floats, of the split
 // stage at j * ldu16 bf16 (hi) and (ncap + j) * ldu16 (lo); the row padding
@@ -200,12 +197,14 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
           if (F32) {
             src = first ? (const void*)(a.U32 + (long)s_col[j] * a.lds + w * 4)
                         : (const void*)(a.xu32[k & 1] + (long)j * n_pad + w * 4);
-          } else {
-            // the first half of an instance's vectors are hi, the second lo
+          } else if (first) {
+            // the launch path's split: the first half of an instance's
+            // vectors are hi, the second lo
             const int hl = w >= nv / 2, w8 = (w - hl * (nv / 2)) * 8;
-            const uint16_t* b0 = first ? (hl ? a.Ulo : a.Uhi) + (long)s_col[j] * a.lds
-                                       : (hl ? a.xul[k & 1] : a.xuh[k & 1]) + (long)j * n_pad;
-            src = b0 + w8;
+            src = (hl ? a.Ulo : a.Uhi) + (long)s_col[j] * a.lds + w8;
+          } else {
+            // packed words: vector w holds elements 4w .. 4w + 3
+            src = a.xpk[k & 1] + (long)j * n_pad + w * 4;
           }
           uv[i] = first ? ld16(src) : ld16c(src);
         }
@@ -233,10 +232,19 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
           const int j = e / nv, w = e % nv;
           if (F32) {
             *reinterpret_cast<u4*>(reinterpret_cast<float*>(ustage) + (long)j * ldu32(n_pad) + w * 4) = uv[i];
-          } else {
+          } else if (first) {
             const int hl = w >= nv / 2, w8 = (w - hl * (nv / 2)) * 8;
             uint16_t* sh = reinterpret_cast<uint16_t*>(ustage) + (long)(hl * ncap + j) * ldu16(n_pad);
             *reinterpret_cast<u4*>(sh + w8) = uv[i];
+          } else {
+            // unpack four (hi, lo) words into four hi and four lo values
+            const u4 v = uv[i];
+            typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+            const u2 hi = {(v[0] & 0xffffu) | (v[1] << 16), (v[2] & 0xffffu) | (v[3] << 16)};
+            const u2 lo = {(v[0] >> 16) | (v[1] & 0xffff0000u), (v[2] >> 16) | (v[3] & 0xffff0000u)};
+            uint16_t* sh = reinterpret_cast<uint16_t*>(ustage) + (long)j * ldu16(n_pad) + w * 4;
+            *reinterpret_cast<u2*>(sh) = hi;
+            *reinterpret_cast<u2*>(sh + (long)ncap * ldu16(n_pad)) = lo;
           }
         }
       }
@@ -365,8 +373,8 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
           stfc(a.xu32[nb] + xo, un);
         } else {
           const uint16_t h = f2bf_t(un);
-          sthc(a.xuh[nb] + xo, h);
-          sthc(a.xul[nb] + xo, f2bf_t(un - bf2f_t(h)));
+          const uint32_t w = (uint32_t)h | ((uint32_t)f2bf_t(un - bf2f_t(h)) << 16);
+          __hip_atomic_store(a.xpk[nb] + xo, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const float d = wn - wo;
         part[0] = d * d;
