@@ -151,3 +151,21 @@ def test_a_planted_sign_mistake_is_caught():
     w_mn = np.linalg.lstsq(A, b, rcond=None)[0]
     wrong = dalm(A, -b, beta=1.0, fixed_iters=1).w[:, 0]
     assert np.linalg.norm(wrong - w_mn) > 1e-3
+
+
+def test_synthetic_recipe_recovers_planted():
+    # the paper's noise-free recipe (Gaussian unit columns, U[-10, 10] nonzeros)
+    # at a small size: the planted x0 is the l1 optimum up to the FP32 rounding
+    # of b (the LP agrees), and both oracles reach the LP optimum
+    from oracle import palm
+    P = dense_p1(m=80, n=100, k=10, N=2, cfg=7, values="uniform10")
+    A = P.A.astype(float)
+    for j in range(2):
+        b = P.b[:, j].astype(float)
+        x0 = P.x0[:, j].astype(float)
+        w_lp, _ = p1_lp(A, b)
+        assert np.linalg.norm(w_lp - x0) < 1e-6 * np.linalg.norm(x0)
+        rd = dalm(A, b, tol=1e-12, max_iter=20000)
+        assert np.linalg.norm(rd.w[:, 0] - w_lp) < 1e-7 * np.linalg.norm(w_lp)
+        rp = palm(A, b, tol=1e-10, max_iter=2000, max_inner=500)
+        assert np.linalg.norm(rp.x[:, 0] - w_lp) < 1e-7 * np.linalg.norm(w_lp)
