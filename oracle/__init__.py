@@ -19,7 +19,9 @@ algorithms for robust face recognition"):
 * ``kkt``     -- optimality certificates (LP duality, Sec. III-A / V-B; the
   Homotopy optimality condition of Sec. III-B for QP_lambda);
 * ``unrolled``-- a fixed number of Algorithm-2 iterations and its exact
-  reverse-mode gradient with respect to b and the dictionary.
+  reverse-mode gradient with respect to b and the dictionary;
+* ``sci``     -- the recognition criterion of the face experiments
+  (Sec. VI-B): subject l1 masses, the sparsity concentration index, label.
 
 Parity status of each function is stated in its docstring; those without an
 independent pin say "parity unpinned".
@@ -28,6 +30,7 @@ from .prox import soft, proj_box, block_soft, proj_ball  # noqa: F401
 from .exact import p1_lp, brute_force_p1, brute_force_qp, qp_fista  # noqa: F401
 from .dalm import dalm, DalmResult, full_matrix  # noqa: F401
 from .palm import palm, PalmResult  # noqa: F401
+from .sci import sci  # noqa: F401
 from .kkt import kkt_report  # noqa: F401
 from .unrolled import (  # noqa: F401
     unrolled_dalm, unrolled_loss, unrolled_grad, unrolled_vjp,
