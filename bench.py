@@ -227,6 +227,19 @@ def main():
                                  "p99": float(np.quantile(err_pl, 0.99)),
                                  "median": float(np.median(err_pl))}
     log(f"rel. err of x vs planted solution, all {N} instances: max {err_pl.max():.2e}")
+    # the recognition criterion of the face experiments (Sec. VI-B) on the
+    # solved batch: every test vector is drawn from one subject's columns
+    from paper_1007_3753_amd import classify
+    ptr = np.arange(0, nd + 1, P.per_class)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, label, score = classify(r.x, ptr)
+    torch.cuda.synchronize()
+    cls_ms = 1e3 * (time.perf_counter() - t)
+    rate = float((label.cpu().numpy() == P.labels).mean())
+    out["recognition"] = {"rate": rate, "ms": round(cls_ms, 3), "subjects": int(len(ptr) - 1),
+                          "score_median": float(score.median())}
+    log(f"recognition (Sec. VI-B criterion): {100 * rate:.1f} % of {N} in {cls_ms:.2f} ms")
     if not args.no_check and args.check_instances > 0:
         from oracle import p1_lp, full_matrix
         Af = full_matrix(P.A, "cab")

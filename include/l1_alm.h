@@ -179,6 +179,28 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
  * BF16 4e-6 (the level where rounding noise stalls the test).             */
 int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n);
 
+/* The recognition criterion of the face experiments (Sec. VI-B), applied to
+ * N representations x (n_dict x N, column-major, ld ldx >= n_dict) of test
+ * vectors over a dictionary whose columns are grouped by subject: subject i
+ * owns columns class_ptr[i] .. class_ptr[i+1]-1 (class_ptr: C + 1 ints,
+ * non-decreasing, class_ptr[0] = 0, class_ptr[C] = n_dict; ranges outside
+ * that are clamped to the columns, a decreasing one counts as empty).
+ * Writes, for instance j:
+ *   mass_dev[i + C*j]  ||delta_i(x_j)||_1, the l1 mass of subject i's
+ *                      coefficients (FP32; may be NULL)
+ *   label_dev[j]       the subject of largest mass (the lowest index among
+ *                      equal masses); -1 when x_j = 0
+ *   score_dev[j]       its sparsity concentration index
+ *                      (C * mass / ||x_j||_1 - 1) / (C - 1); 0 when x_j = 0
+ * Masses and the norm are summed in FP64 in a fixed order, so the result is
+ * reproducible and the label is decided in FP64.  For the cross-and-bouquet
+ * form pass x only (the e block is not a subject).  Needs no plan.
+ * Errors: L1_EINVAL for N < 0, n_dict < 1, ldx < n_dict, C outside
+ * [2, L1_CLASSIFY_MAX_SUBJECTS] or a NULL x / class_ptr / label / score.   */
+#define L1_CLASSIFY_MAX_SUBJECTS 4096
+int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* class_ptr_dev,
+                    int C, float* mass_dev, int* label_dev, float* score_dev, void* stream);
+
 /* Release the plan and all device memory it owns. */
 int l1_alm_destroy(l1_alm_plan_t plan);
 

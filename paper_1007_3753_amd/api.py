@@ -168,6 +168,27 @@ class Plan:
         return dict(zip(self.STAT_KEYS, list(out)))
 
 
+def classify(x, class_ptr):
+    """The recognition criterion of the face experiments (Sec. VI-B) on the
+    GPU: ``x`` (n_dict, N) representations, ``class_ptr`` (C + 1,) column
+    ranges of the subjects.  Returns (mass (C, N), label (N,), score (N,))
+    from l1_alm_classify."""
+    lib = _lib.load()
+    x = torch.as_tensor(x)
+    if x.dim() == 1:
+        x = x[:, None]
+    xc = _colmajor(x, x.shape[0])
+    N, n_dict = int(xc.shape[0]), int(xc.shape[1])
+    ptr = torch.as_tensor(class_ptr, dtype=torch.int32, device=xc.device).contiguous()
+    C = int(ptr.numel()) - 1
+    mass = torch.empty(N, C, device=xc.device, dtype=torch.float32)
+    label = torch.empty(N, device=xc.device, dtype=torch.int32)
+    score = torch.empty(N, device=xc.device, dtype=torch.float32)
+    _lib.check(lib.l1_alm_classify(_ptr(xc), n_dict, n_dict, N, _ptr(ptr), C, _ptr(mass),
+                                   _ptr(label), _ptr(score), _stream()))
+    return mass.t(), label, score
+
+
 class DALMUnrolled(torch.autograd.Function):
     """``x, e = DALMUnrolled.apply(b, B, iters, checkpoint_every)``: exactly
     ``iters`` dual ALM iterations (Algorithm 2) on the cross-and-bouquet

@@ -366,6 +366,25 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N, const flo
   }
 }
 
+int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* class_ptr_dev,
+                    int C, float* mass_dev, int* label_dev, float* score_dev, void* stream) {
+  try {
+    L1_REQUIRE(N >= 0 && n_dict >= 1 && ldx >= n_dict, "bad n_dict, ldx or N");
+    L1_REQUIRE(C >= 2 && C <= L1_CLASSIFY_MAX_SUBJECTS, "C must be in [2, 4096]");
+    if (N == 0) return L1_OK;
+    L1_REQUIRE(x_dev && class_ptr_dev && label_dev && score_dev,
+               "x, class_ptr, label and score must be non-NULL");
+    classify(reinterpret_cast<hipStream_t>(stream), x_dev, ldx, n_dict, N, class_ptr_dev, C,
+             mass_dev, label_dev, score_dev);
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
 int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n) {
   try {
     Plan* p = reinterpret_cast<Plan*>(plan);

@@ -154,6 +154,10 @@ struct GemmArgs {
   long long* stat;             // [3 + prec] += live columns, [prec] += column tiles
 };
 
+// The recognition criterion of Sec. VI-B (csrc/classify.hip).
+void classify(hipStream_t s, const float* x, int ldx, int n_dict, int N, const int* ptr, int C,
+              float* mass, int* label, float* score);
+
 // Number of column tiles a launch must cover for up to n columns split over
 // the phases (each phase range is padded to a multiple of TILE).
 inline int col_tiles_for(int n) { return (n + TILE - 1) / TILE + NPHASE - 1; }
