@@ -15,4 +15,6 @@ from .generators import (  # noqa: F401
     cab_instances,
     cab_problem,
     tiny_dense,
+    AlignProblem,
+    align_problem,
 )

@@ -186,3 +186,73 @@ def tiny_dense(m: int, n: int, N: int = 1, key: int = 0, k: Optional[int] = None
         X = X.astype(np.float32)
         b = (A.astype(np.float64) @ X.astype(np.float64)).astype(np.float32)
     return Problem(A=A, b=b, structure="dense", problem="p1", x0=X, meta={"key": key})
+
+
+@dataclass
+class AlignProblem:
+    """A batch of alignment l1 problems ``min ||e||_1 s.t. b = B_j w + e``,
+    each instance with its own m x k dictionary (eq. (align-simple))."""
+    B: np.ndarray        # (N, m, k) float32: B[j] is instance j's dictionary
+    b: np.ndarray        # (m, N) float32
+    w0: np.ndarray       # (k, N) planted coefficients
+    e0: np.ndarray       # (m, N) planted sparse error (the occluding block)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return self.b.shape[0]
+
+    @property
+    def k(self) -> int:
+        return self.B.shape[2]
+
+    @property
+    def N(self) -> int:
+        return self.b.shape[1]
+
+
+def align_problem(N: int = 1000, h: int = 40, wd: int = 30, n_img: int = 7,
+                  occl: float = 0.10, cfg: int = 6, first: int = 0) -> AlignProblem:
+    """Alignment-shaped instances (Sec. II-B, Sec. VI-C), a synthetic stand-in
+    for the Multi-PIE alignment experiment: an h x wd image grid (m = h*wd),
+    ``B_j = [A_j, -J_j]`` with ``n_img`` training images of one subject (a
+    smooth nonnegative mean image plus small per-image variation, unit norm)
+    and the four columns of a similarity transform's Jacobian of the mean
+    image (x and y derivative, rotation, scale; unit norm); ``b = B_j w0 + e0``
+    with w0 a convex combination of the images plus a small transform step,
+    and e0 the difference made by a randomly placed block covering ``occl``
+    of the image whose pixels are replaced by U[0, 1] values."""
+    m = h * wd
+    k = n_img + 4
+    yy, xx = np.meshgrid(np.arange(h) - (h - 1) / 2.0, np.arange(wd) - (wd - 1) / 2.0, indexing="ij")
+    Bs = np.empty((N, m, k))
+    b = np.empty((m, N))
+    w0 = np.zeros((k, N))
+    e0 = np.zeros((m, N))
+    bh = max(1, int(round(np.sqrt(occl * m * h / wd))))
+    bw = max(1, int(round(occl * m / bh)))
+    for jj in range(N):
+        j = first + jj
+        r = _rng(cfg, 0, j)
+        # smooth mean image: a few random Gaussian bumps on a bright base
+        img = 0.3 * np.ones((h, wd))
+        for _ in range(6):
+            cy, cx = r.uniform(-h / 2, h / 2), r.uniform(-wd / 2, wd / 2)
+            s = r.uniform(3.0, 8.0)
+            img += r.uniform(0.2, 0.7) * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * s * s))
+        A = np.maximum(img.reshape(-1, 1) + 0.05 * r.standard_normal((m, n_img)), 0.0)
+        gy, gx = np.gradient(img)
+        J = np.stack([gx, gy, xx * gy - yy * gx, xx * gx + yy * gy], axis=-1).reshape(m, 4)
+        B = np.concatenate([_unit_columns(A), -_unit_columns(J)], axis=1)
+        w = np.concatenate([r.dirichlet(np.ones(n_img)), 0.05 * r.standard_normal(4)])
+        clean = B @ w
+        y0, x0 = int(r.integers(0, h - bh + 1)), int(r.integers(0, wd - bw + 1))
+        vec = clean.reshape(h, wd).copy()
+        vec[y0:y0 + bh, x0:x0 + bw] = r.uniform(0.0, 1.0, (bh, bw))
+        vec = vec.reshape(-1)
+        Bs[jj] = B
+        b[:, jj] = vec
+        w0[:, jj] = w
+        e0[:, jj] = vec - clean
+    return AlignProblem(B=Bs.astype(np.float32), b=b.astype(np.float32), w0=w0.astype(np.float32),
+                        e0=e0.astype(np.float32), meta={"cfg": cfg, "occl": occl, "h": h, "w": wd})
