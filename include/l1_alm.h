@@ -201,6 +201,39 @@ int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n);
 int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* class_ptr_dev,
                     int C, float* mass_dev, int* label_dev, float* score_dev, void* stream);
 
+/* The l1 problem of the alignment step (Sec. II-B, the linearised
+ * registration problem; Sec. VI-C):  min ||e||_1  s.t.  b_j = B_j w + e,
+ * for N instances, each with its own small m x k dictionary B_j (the
+ * training images of one subject and the image Jacobian of the transform),
+ * solved by the primal ALM with the exact least-squares w-step (Algorithm 1
+ * with w unpenalised, as the alignment experiment runs it):
+ *   e <- shrink(b - B w + theta/xi, 1/xi),  w <- (B^T B)^{-1} B^T (b - e + theta/xi),
+ *   theta <- theta + xi (b - B w - e),
+ * from w = 0, theta = 0, xi = 2m / ||b_j||_1 (1 when b_j = 0), stopping when
+ * ||w_new - w|| < tol ||w|| (strict), or after exactly -max_iter iterations
+ * with no test when max_iter < 0.  Needs no plan.
+ *   B_dev      N consecutive column-major m x k matrices (B_j at B_dev + j*m*k)
+ *   b_dev      m x N column-major, leading dimension ldb >= m
+ *   w_dev      k x N column-major (leading dimension k), written
+ *   e_dev      m x N column-major, leading dimension lde >= m, written
+ *   iters_dev, status_dev  N ints each, written (L1_CONVERGED, L1_MAXITER;
+ *              L1_NONFINITE for a non-finite w or a rank-deficient B_j,
+ *              which is reported with w = 0, e = b and iters = 0)
+ * B^T B is formed and inverted once per instance in FP64, and B^T s is
+ * summed in FP64; the rest runs in FP32.  All buffers are device memory
+ * owned by the caller; the call is asynchronous on `stream`.
+ * Limits: 1 <= k <= L1_ALIGN_MAX_K, 1 <= m <= L1_ALIGN_MAX_M,
+ * m * k <= L1_ALIGN_MAX_MK (the dictionary is held in LDS).
+ * Errors: L1_EINVAL for sizes outside those limits, N < 0, ldb or lde < m,
+ * max_iter = 0, tol not positive and finite (when max_iter > 0), or a
+ * NULL buffer.                                                            */
+#define L1_ALIGN_MAX_K 16
+#define L1_ALIGN_MAX_M 2048
+#define L1_ALIGN_MAX_MK 24576
+int l1_alm_align(const float* B_dev, int m, int k, int N, const float* b_dev, int ldb, float tol,
+                 int max_iter, float* w_dev, float* e_dev, int lde, int* iters_dev, int* status_dev,
+                 void* stream);
+
 /* Release the plan and all device memory it owns. */
 int l1_alm_destroy(l1_alm_plan_t plan);
 

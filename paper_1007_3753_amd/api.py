@@ -189,6 +189,37 @@ def classify(x, class_ptr):
     return mass.t(), label, score
 
 
+def align(B, b, tol=1e-3, max_iter=1000, fixed_iters=None):
+    """The l1 problem of the alignment step (Sec. II-B; Sec. VI-C) on the
+    GPU: ``B`` (N, m, k) per-instance dictionaries, ``b`` (m, N).  Runs the
+    primal ALM of l1_alm_align until ||w_new - w|| < tol ||w|| (at most
+    ``max_iter`` iterations), or exactly ``fixed_iters`` iterations.
+    Returns (w (k, N), e (m, N), iters (N,), status (N,))."""
+    lib = _lib.load()
+    B = torch.as_tensor(B)
+    b = torch.as_tensor(b)
+    if b.dim() == 1:
+        b = b[:, None]
+    if B.dim() == 2:
+        B = B[None]
+    N, m, k = (int(v) for v in B.shape)
+    if b.shape != (m, N):
+        raise ValueError(f"b must be ({m}, {N}), got {tuple(b.shape)}")
+    if not B.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    # each B_j column-major: (N, k, m) row-major holds B_j^T contiguously
+    Bc = B.to(torch.float32).transpose(1, 2).contiguous()
+    bc = _colmajor(b, m)
+    w = torch.empty(N, k, device=bc.device, dtype=torch.float32)
+    e = torch.empty(N, m, device=bc.device, dtype=torch.float32)
+    iters = torch.empty(N, device=bc.device, dtype=torch.int32)
+    status = torch.empty(N, device=bc.device, dtype=torch.int32)
+    cap = -int(fixed_iters) if fixed_iters is not None else int(max_iter)
+    _lib.check(lib.l1_alm_align(_ptr(Bc), m, k, N, _ptr(bc), m, float(tol), cap, _ptr(w), _ptr(e), m,
+                                _ptr(iters), _ptr(status), _stream()))
+    return w.t(), e.t(), iters, status
+
+
 class DALMUnrolled(torch.autograd.Function):
     """``x, e = DALMUnrolled.apply(b, B, iters, checkpoint_every)``: exactly
     ``iters`` dual ALM iterations (Algorithm 2) on the cross-and-bouquet

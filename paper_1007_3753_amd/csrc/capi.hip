@@ -385,6 +385,33 @@ int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* c
   }
 }
 
+int l1_alm_align(const float* B_dev, int m, int k, int N, const float* b_dev, int ldb, float tol,
+                 int max_iter, float* w_dev, float* e_dev, int lde, int* iters_dev, int* status_dev,
+                 void* stream) {
+  static_assert(L1_ALIGN_MAX_K == ALIGN_KMAX && L1_ALIGN_MAX_M == 256 * ALIGN_R &&
+                    L1_ALIGN_MAX_MK == ALIGN_MK_MAX,
+                "alignment limits");
+  try {
+    L1_REQUIRE(N >= 0, "N must be >= 0");
+    L1_REQUIRE(k >= 1 && k <= L1_ALIGN_MAX_K, "k must be in [1, 16]");
+    L1_REQUIRE(m >= 1 && m <= L1_ALIGN_MAX_M, "m must be in [1, 2048]");
+    L1_REQUIRE((long)m * k <= L1_ALIGN_MAX_MK, "m * k must be <= 24576");
+    L1_REQUIRE(ldb >= m && lde >= m, "ldb and lde must be >= m");
+    L1_REQUIRE(max_iter != 0, "max_iter must be non-zero");
+    L1_REQUIRE(max_iter < 0 || (std::isfinite(tol) && tol > 0.0f), "tol must be positive and finite");
+    if (N == 0) return L1_OK;
+    L1_REQUIRE(B_dev && b_dev && w_dev && e_dev && iters_dev && status_dev, "NULL buffer");
+    align_solve(reinterpret_cast<hipStream_t>(stream), B_dev, m, k, N, b_dev, ldb, tol, max_iter, w_dev,
+                e_dev, lde, iters_dev, status_dev);
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
 int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n) {
   try {
     Plan* p = reinterpret_cast<Plan*>(plan);

@@ -154,6 +154,14 @@ struct GemmArgs {
   long long* stat;             // [3 + prec] += live columns, [prec] += column tiles
 };
 
+// The alignment l1 problem of Sec. II-B (csrc/align.hip): per instance its
+// own m x k dictionary, k <= ALIGN_KMAX, m <= 256 * ALIGN_R, m * k <= ALIGN_MK_MAX.
+constexpr int ALIGN_KMAX = 16;
+constexpr int ALIGN_R = 8;
+constexpr int ALIGN_MK_MAX = 24576;
+void align_solve(hipStream_t s, const float* B, int m, int k, int N, const float* b, int ldb, float tol,
+                 int max_iter, float* w, float* e, int lde, int* iters, int* status);
+
 // The recognition criterion of Sec. VI-B (csrc/classify.hip).
 void classify(hipStream_t s, const float* x, int ldx, int n_dict, int N, const int* ptr, int C,
               float* mass, int* label, float* score);
