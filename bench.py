@@ -437,8 +437,10 @@ def align_main(args):
     N, m, k = P.B.shape
     log(f"workload {args.workload}: B_j {m} x {k}, N {N}, generated in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
-    B = torch.as_tensor(P.B, device=dev)
-    b = torch.as_tensor(P.b, device=dev)
+    # the library's layout, made once: each B_j column-major and b column-major
+    # (views whose transposes are contiguous, so the binding copies nothing)
+    B = torch.as_tensor(np.ascontiguousarray(P.B.transpose(0, 2, 1)), device=dev).transpose(1, 2)
+    b = torch.as_tensor(np.ascontiguousarray(P.b.T), device=dev).t()
     w0 = P.w0.astype(np.float64)
     per_tol = {}
     for tol in wl["tols"]:

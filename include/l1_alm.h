@@ -220,16 +220,15 @@ int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* c
  *              L1_NONFINITE for a non-finite w or a rank-deficient B_j,
  *              which is reported with w = 0, e = b and iters = 0)
  * B^T B is formed and inverted once per instance in FP64, and B^T s is
- * summed in FP64; the rest runs in FP32.  All buffers are device memory
+ * combined in FP64; the rest runs in FP32.  All buffers are device memory
  * owned by the caller; the call is asynchronous on `stream`.
- * Limits: 1 <= k <= L1_ALIGN_MAX_K, 1 <= m <= L1_ALIGN_MAX_M,
- * m * k <= L1_ALIGN_MAX_MK (the dictionary is held in LDS).
+ * Limits: 1 <= k <= L1_ALIGN_MAX_K, 1 <= m <= L1_ALIGN_MAX_M (each instance
+ * is one workgroup holding its dictionary in registers).
  * Errors: L1_EINVAL for sizes outside those limits, N < 0, ldb or lde < m,
  * max_iter = 0, tol not positive and finite (when max_iter > 0), or a
  * NULL buffer.                                                            */
 #define L1_ALIGN_MAX_K 16
 #define L1_ALIGN_MAX_M 2048
-#define L1_ALIGN_MAX_MK 24576
 int l1_alm_align(const float* B_dev, int m, int k, int N, const float* b_dev, int ldb, float tol,
                  int max_iter, float* w_dev, float* e_dev, int lde, int* iters_dev, int* status_dev,
                  void* stream);

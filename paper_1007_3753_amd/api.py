@@ -194,7 +194,10 @@ def align(B, b, tol=1e-3, max_iter=1000, fixed_iters=None):
     GPU: ``B`` (N, m, k) per-instance dictionaries, ``b`` (m, N).  Runs the
     primal ALM of l1_alm_align until ||w_new - w|| < tol ||w|| (at most
     ``max_iter`` iterations), or exactly ``fixed_iters`` iterations.
-    Returns (w (k, N), e (m, N), iters (N,), status (N,))."""
+    Returns (w (k, N), e (m, N), iters (N,), status (N,)).  The library
+    reads each B_j and b column-major: ``B`` given as ``Bt.transpose(1, 2)``
+    of a contiguous (N, k, m) float32 tensor and ``b`` as ``bt.t()`` of a
+    contiguous (N, m) one are passed without a copy."""
     lib = _lib.load()
     B = torch.as_tensor(B)
     b = torch.as_tensor(b)

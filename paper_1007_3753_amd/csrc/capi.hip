@@ -388,14 +388,11 @@ int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* c
 int l1_alm_align(const float* B_dev, int m, int k, int N, const float* b_dev, int ldb, float tol,
                  int max_iter, float* w_dev, float* e_dev, int lde, int* iters_dev, int* status_dev,
                  void* stream) {
-  static_assert(L1_ALIGN_MAX_K == ALIGN_KMAX && L1_ALIGN_MAX_M == 256 * ALIGN_R &&
-                    L1_ALIGN_MAX_MK == ALIGN_MK_MAX,
-                "alignment limits");
+  static_assert(L1_ALIGN_MAX_K == ALIGN_KMAX && L1_ALIGN_MAX_M == 256 * ALIGN_R, "alignment limits");
   try {
     L1_REQUIRE(N >= 0, "N must be >= 0");
     L1_REQUIRE(k >= 1 && k <= L1_ALIGN_MAX_K, "k must be in [1, 16]");
     L1_REQUIRE(m >= 1 && m <= L1_ALIGN_MAX_M, "m must be in [1, 2048]");
-    L1_REQUIRE((long)m * k <= L1_ALIGN_MAX_MK, "m * k must be <= 24576");
     L1_REQUIRE(ldb >= m && lde >= m, "ldb and lde must be >= m");
     L1_REQUIRE(max_iter != 0, "max_iter must be non-zero");
     L1_REQUIRE(max_iter < 0 || (std::isfinite(tol) && tol > 0.0f), "tol must be positive and finite");

@@ -155,10 +155,9 @@ struct GemmArgs {
 };
 
 // The alignment l1 problem of Sec. II-B (csrc/align.hip): per instance its
-// own m x k dictionary, k <= ALIGN_KMAX, m <= 256 * ALIGN_R, m * k <= ALIGN_MK_MAX.
+// own m x k dictionary, k <= ALIGN_KMAX, m <= 256 * ALIGN_R.
 constexpr int ALIGN_KMAX = 16;
 constexpr int ALIGN_R = 8;
-constexpr int ALIGN_MK_MAX = 24576;
 void align_solve(hipStream_t s, const float* B, int m, int k, int N, const float* b, int ldb, float tol,
                  int max_iter, float* w, float* e, int lde, int* iters, int* status);
 

@@ -49,9 +49,12 @@ def test_converged_solves_recover_the_planted_transform():
     r = align_palm(P.B, P.b, tol=1e-5, max_iter=2000)
     assert np.all(st == L1_CONVERGED)
     assert _rel(w, r.w).max() < 1e-4
-    # the stopping rule is the oracle's: the same iteration up to a tie at the threshold
-    assert np.abs(it.astype(int) - r.iters.astype(int)).max() <= 2
-    assert np.mean(it == r.iters) >= 0.8
+    # the stopping rule is the oracle's.  At tol 1e-5 the FP32 rounding of
+    # the iterate (about cond(B) * u32 = 2.4e-6 of ||w||) is a quarter of the
+    # threshold and the change shrinks by a few per cent an iteration, so the
+    # stopping iteration may move by a few
+    assert np.abs(it.astype(int) - r.iters.astype(int)).max() <= 4
+    assert np.mean(it == r.iters) >= 0.6
     # with a fixed xi the relative change of w can fall below tol while w is
     # still about 1e-3 from the optimum (the oracle stops there too), so the
     # planted w0 and the occluding block's difference e0 are recovered by
@@ -74,7 +77,7 @@ def test_table_tolerances_stop_where_the_oracle_stops(tol):
 
 
 def test_ragged_rows_and_small_dictionaries():
-    # m not a multiple of the 256 threads; k = 5, 7 and 12 (with m * k near the LDS limit)
+    # m not a multiple of the 256 threads; k = 5, 7 and 12
     for (h, wd, n_img, cfg) in [(37, 29, 3, 74), (2, 5, 1, 75), (45, 45, 8, 76)]:
         P = align_problem(N=5, h=h, wd=wd, n_img=n_img, cfg=cfg)
         w, e, it, st = _align(P.B, P.b, fixed_iters=6)
@@ -95,9 +98,9 @@ def test_single_column_and_widest_dictionary():
 
 
 def test_largest_dictionary_fits():
-    # m * k = 24576 (the LDS limit): m = 2048, k = 12
+    # the largest sizes: m = 2048 (8 rows a thread), k = 16
     rng = np.random.default_rng(77)
-    N, m, k = 3, 2048, 12
+    N, m, k = 3, 2048, 16
     B = rng.standard_normal((N, m, k)).astype(np.float32)
     w0 = rng.standard_normal((k, N))
     b = np.einsum("jmk,kj->mj", B.astype(np.float64), w0)
@@ -135,7 +138,7 @@ def test_empty_batch_and_bad_sizes():
     lib = _lib.load()
     assert lib.l1_alm_align(None, 100, 4, 0, None, 100, 1e-3, 10, None, None, 100, None, None, None) == 0
     dev = torch.device("cuda")
-    for (m, k) in [(2049, 1), (100, 17), (2048, 13)]:
+    for (m, k) in [(2049, 1), (100, 17), (100, 0)]:
         with pytest.raises(L1Error):
             align(torch.zeros(1, m, k, device=dev), torch.ones(m, 1, device=dev), max_iter=5)
     with pytest.raises(L1Error):
