@@ -18,14 +18,13 @@
 //   reduce   the partials through LDS: the 16 lanes of a row of the wave
 //            take one column, add 16 partials each in FP64 and then sum
 //            over the row with DPP rotations
-//   w-step   thread (t, d) = (tid / 16, tid % 16) holds (B^T B)^{-1}[t][d]
-//            (FP64, formed once) and forms w_t = sum_d Ginv[t][d] g_d with
-//            the same row sum; the row also leaves (w_t - w_t_old)^2 and
-//            w_t_old^2
-//   test     every thread reads the new w and those squares from LDS and
-//            takes the same stopping decision (FP64, a fixed order)
+//   w-step   every wave forms all of w = Ginv g: lane (t, d) = (lane / 16
+//            + 4 pass, lane % 16) holds (B^T B)^{-1}[t][d] (FP64, formed
+//            once), the row sum gives w_t, read into scalar registers
+//   test     so every wave holds the same w (FP64) and takes the same
+//            stopping decision, with no barrier
 //   rows     B w (FP32) and the theta-step.
-// Three workgroup barriers per iteration.  B^T B is formed once on the FP64
+// Two workgroup barriers per iteration.  B^T B is formed once on the FP64
 // matrix cores from the FP32 dictionary (exact products) and B^T s is
 // combined in FP64, so the normal equations do not square the dictionary's
 // condition number in FP32.
@@ -79,15 +78,14 @@ __global__ __launch_bounds__(AL_THREADS) void align_kernel(const float* Bg, int 
     float p[KP][AL_THREADS + 16];
   } s_u;
   __shared__ double s_g[16];
-  __shared__ double s_aug[ALIGN_KMAX][2 * ALIGN_KMAX];
-  __shared__ double s_fac[ALIGN_KMAX], s_diag[ALIGN_KMAX];
-  __shared__ double s_w[16], s_dw[16], s_wo[16];
+  __shared__ double s_aug[2][ALIGN_KMAX][2 * ALIGN_KMAX];
+  __shared__ double s_diag[ALIGN_KMAX];
   __shared__ int s_flag;
   const int j = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63;
   const int slot = (tid >> 6) * 4 + (lane >> 4);   // which row of 16 lanes
   const bool row_lead = (lane & 15) == 0;
-  const int tt = tid >> 4, dd = tid & 15;            // the (t, d) pair of the w-step
+  const int dd = tid & 15;                           // the column d of the w-step
   const float* B = Bg + (long)j * m * k;
   const float* bj = bg + (long)j * ldb;
 
@@ -110,7 +108,6 @@ __global__ __launch_bounds__(AL_THREADS) void align_kernel(const float* Bg, int 
   }
   n1 = row_sum(n1);
   if (row_lead) s_red[slot] = n1;
-  if (tid < 16) s_w[tid] = 0.0;
   __syncthreads();
   n1 = 0.0;
 #pragma unroll
@@ -148,32 +145,42 @@ __global__ __launch_bounds__(AL_THREADS) void align_kernel(const float* Bg, int 
     for (int t = tid; t < k * k; t += AL_THREADS) {
       const int i = t / k, c = t % k;
       const double g = (s_u.gw[0][i][c] + s_u.gw[1][i][c]) + (s_u.gw[2][i][c] + s_u.gw[3][i][c]);
-      s_aug[i][c] = g;
-      s_aug[i][k + c] = i == c ? 1.0 : 0.0;
+      s_aug[0][i][c] = g;
+      s_aug[0][i][k + c] = i == c ? 1.0 : 0.0;
       if (i == c) s_diag[i] = g;
     }
   }
 
-  // its inverse: Gauss-Jordan on [G | I] in LDS, the row operations of a
-  // pivot spread over the threads; a pivot below 1e-12 of its diagonal entry
-  // marks a rank-deficient dictionary
+  // its inverse: Gauss-Jordan on [G | I], each pivot one step from one LDS
+  // copy of the augmented matrix into the other (every entry of the new one
+  // depends only on the old one), one barrier a step; a pivot below 1e-12 of
+  // its diagonal entry marks a rank-deficient dictionary
   if (tid == 0) s_flag = 1;
   __syncthreads();
-  for (int pv = 0; pv < k; ++pv) {
-    const double piv = s_aug[pv][pv];
-    if (!(piv > 1e-12 * s_diag[pv])) {
-      if (tid == 0) s_flag = 0;
-      break;   // uniform: every thread read the same pivot
+  int cur = 0;
+  {
+    const int w2 = 2 * k;
+    const int r0 = tid / w2, c0 = tid % w2;                                 // entry tid
+    const int r1 = (tid + AL_THREADS) / w2, c1 = (tid + AL_THREADS) % w2;   // entry tid + 256
+    const bool has0 = tid < k * w2, has1 = tid + AL_THREADS < k * w2;
+    for (int pv = 0; pv < k; ++pv) {
+      const double piv = s_aug[cur][pv][pv];
+      if (!(piv > 1e-12 * s_diag[pv])) {
+        if (tid == 0) s_flag = 0;
+        break;   // uniform: every thread read the same pivot
+      }
+      const double ip = 1.0 / piv;
+      if (has0) {
+        const double pr = s_aug[cur][pv][c0] * ip;
+        s_aug[cur ^ 1][r0][c0] = r0 == pv ? pr : s_aug[cur][r0][c0] - s_aug[cur][r0][pv] * pr;
+      }
+      if (has1) {
+        const double pr = s_aug[cur][pv][c1] * ip;
+        s_aug[cur ^ 1][r1][c1] = r1 == pv ? pr : s_aug[cur][r1][c1] - s_aug[cur][r1][pv] * pr;
+      }
+      __syncthreads();
+      cur ^= 1;
     }
-    if (tid < k) s_fac[tid] = s_aug[tid][pv];
-    __syncthreads();
-    if (tid < 2 * k) s_aug[pv][tid] /= piv;
-    __syncthreads();
-    for (int t = tid; t < 2 * k * k; t += AL_THREADS) {
-      const int r = t / (2 * k), c = t % (2 * k);
-      if (r != pv) s_aug[r][c] -= s_fac[r] * s_aug[pv][c];
-    }
-    __syncthreads();
   }
   __syncthreads();
   if (!s_flag) {
@@ -185,7 +192,17 @@ __global__ __launch_bounds__(AL_THREADS) void align_kernel(const float* Bg, int 
     }
     return;
   }
-  const double ginv = (tt < k && dd < k) ? s_aug[tt][k + dd] : 0.0;
+  // Ginv[t][d] for t = lane / 16 + 4 pass, d = lane % 16 (zero past k)
+  constexpr int NP = KP / 4;   // passes of the w-step
+  double ginv[NP];
+#pragma unroll
+  for (int ps = 0; ps < NP; ++ps) {
+    const int t = (lane >> 4) + 4 * ps;
+    ginv[ps] = (t < k && dd < k) ? s_aug[cur][t][k + dd] : 0.0;
+  }
+  double w[KP];   // the current w, the same in every lane of every wave
+#pragma unroll
+  for (int d = 0; d < KP; ++d) w[d] = 0.0;
 
   int it = 0, st = L1_MAXITER;
   for (it = 1; it <= cap; ++it) {
@@ -217,26 +234,23 @@ __global__ __launch_bounds__(AL_THREADS) void align_kernel(const float* Bg, int 
       if (q == 0 && c < KP) s_g[c] = g;
     }
     __syncthreads();
-    // w-step: w_t = sum_d Ginv[t][d] g_d in the row of 16 lanes of t
-    {
-      const double wt = row_sum(ginv * (dd < k ? s_g[dd] : 0.0));
-      const double wo = s_w[tt & 15];
-      if (tt < k) {
-        if (dd == 0) s_w[tt] = wt;
-        if (dd == 1) s_dw[tt] = (wt - wo) * (wt - wo);
-        if (dd == 2) s_wo[tt] = wo * wo;
-      }
-    }
-    __syncthreads();
+    // w-step, in every wave: w_t = sum_d Ginv[t][d] g_d as the row sum of
+    // row t % 4 in pass t / 4, taken from the row's first lane
+    const double gd = dd < k ? s_g[dd] : 0.0;
     double dw2 = 0.0, w2 = 0.0;
     float wf[KP];
 #pragma unroll
-    for (int d = 0; d < KP; ++d) {
-      wf[d] = 0.0f;
-      if (d < k) {
-        dw2 += s_dw[d];
-        w2 += s_wo[d];
-        wf[d] = (float)s_w[d];
+    for (int ps = 0; ps < NP; ++ps) {
+      const double v = row_sum(ginv[ps] * gd);
+#pragma unroll
+      for (int t4 = 0; t4 < 4; ++t4) {
+        const int t = 4 * ps + t4;
+        const double wt = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * t4),
+                                           __builtin_amdgcn_readlane(__double2loint(v), 16 * t4));
+        dw2 += (wt - w[t]) * (wt - w[t]);
+        w2 += w[t] * w[t];
+        w[t] = wt;
+        wf[t] = (float)wt;
       }
     }
     // theta-step with t = B w (kept for the next e-step)
@@ -258,7 +272,13 @@ __global__ __launch_bounds__(AL_THREADS) void align_kernel(const float* Bg, int 
     }
   }
   if (it > cap) it = cap;
-  if (tid < k) wg[(long)j * k + tid] = (float)s_w[tid];
+  if (tid < k) {
+    float wv = 0.0f;
+#pragma unroll
+    for (int d = 0; d < KP; ++d)
+      if (d == tid) wv = (float)w[d];
+    wg[(long)j * k + tid] = wv;
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = tid + AL_THREADS * r;
