@@ -81,10 +81,10 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_record(src_hash):
-    """HBM bytes per launch of the iteration kernel from the committed PMC
-    summary, if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "dalm_iteration_traffic.json")
+def traffic_record(src_hash, name="dalm_iteration_traffic.json"):
+    """HBM bytes per launch of a kernel from the committed PMC summary, if
+    it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -94,9 +94,9 @@ def traffic_record(src_hash):
     return rec
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=("iter.hip", "internal.h", "tail.hip", "tail.h", "dalm_test.h")):
     h = hashlib.sha256()
-    for f in ("iter.hip", "internal.h", "tail.hip", "tail.h", "dalm_test.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_1007_3753_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -489,8 +489,10 @@ def align_main(args):
     t_s = r["ms"] / 1e3
     peak = (f32 + f64) / (f32 / 157.3e12 + f64 / 78.6e12) / 1e12
     achieved = (f32 + f64) / t_s / 1e12
+    trec = traffic_record(kernel_source_hash(("align.hip", "internal.h")), "align_traffic.json")
+    traffic = None if trec is None else trec.get("hbm_bytes_per_launch_at_workload", {}).get(args.workload)
     out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
-                       "frac": round(achieved / peak, 4), "traffic": None,
+                       "frac": round(achieved / peak, 4), "traffic": traffic,
                        "kernel": "align_kernel (one launch per batch), HIP events",
                        "avg_launch_us": round(1e3 * r["ms"], 2), "launches_timed": args.steps,
                        "hbm_bytes_per_launch": N * (m * k + 2 * m + k + 2) * 4,
@@ -509,6 +511,13 @@ def align_main(args):
             "value": round(N / dt, 2), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"all {N} instances, FP64 NumPy PALM, same tol; {dt:.1f} s, "
                       f"iterations mean {o.iters.mean():.2f}"}
+    if args.copy_calibration:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = x.numel() * 4
     print(json.dumps(out), flush=True)
 
 
