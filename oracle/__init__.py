@@ -22,6 +22,7 @@ algorithms for robust face recognition"):
   reverse-mode gradient with respect to b and the dictionary;
 * ``sci``     -- the recognition criterion of the face experiments
   (Sec. VI-B): subject l1 masses, the sparsity concentration index, label;
+  and the per-subject residuals of the classifier the paper builds on;
 * ``align``   -- the l1 problem of the alignment step (Sec. II-B, eq.
   (align-simple)): its LP, brute force, and PALM as Sec. VI-C runs it.
 
@@ -32,7 +33,7 @@ from .prox import soft, proj_box, block_soft, proj_ball  # noqa: F401
 from .exact import p1_lp, brute_force_p1, brute_force_qp, qp_fista  # noqa: F401
 from .dalm import dalm, DalmResult, full_matrix  # noqa: F401
 from .palm import palm, PalmResult  # noqa: F401
-from .sci import sci  # noqa: F401
+from .sci import sci, class_residuals  # noqa: F401
 from .align import align_lp, align_brute, align_palm  # noqa: F401
 from .kkt import kkt_report  # noqa: F401
 from .unrolled import (  # noqa: F401

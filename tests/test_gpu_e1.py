@@ -60,3 +60,25 @@ def test_palm_iterates_match_oracle():
     x = r.x.cpu().numpy()[:, 0].astype(np.float64)
     # FP32 over 300 FISTA steps
     assert np.linalg.norm(x - o.x[:, 0]) / np.linalg.norm(o.x[:, 0]) < 1e-4
+
+
+def test_adm_recovers_planted():
+    # ADM: PALM with one FISTA step per outer step (Sec. V-A); on Gaussian data
+    # it converges (the oracle stops after ~180 outer steps at this tolerance)
+    P = dense_p1(m=800, n=1000, k=100, N=20, cfg=5, values="uniform10")
+    pl = _plan(P.A, structure="dense", method="palm", precision="fp32", max_batch=20, max_inner=1)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), tol=1e-6, max_iter=20000)
+    assert np.all(r.status.cpu().numpy() == 0)
+    assert r.iters.cpu().numpy().max() < 1000
+    err = _rel_cols(r.x.cpu().numpy().astype(np.float64), P.x0.astype(np.float64))
+    assert err.max() < 1e-5
+
+
+def test_adm_iterates_match_oracle():
+    # 60 outer steps of one FISTA step each, instance 0
+    P = dense_p1(m=800, n=1000, k=100, N=20, cfg=5, values="uniform10")
+    pl = _plan(P.A, structure="dense", method="palm", precision="fp32", max_batch=20, max_inner=1)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-60)
+    o = oracle_palm(P.A, P.b[:, :1], structure="dense", fixed_outer=60, fixed_inner=1)
+    x = r.x.cpu().numpy()[:, 0].astype(np.float64)
+    assert np.linalg.norm(x - o.x[:, 0]) / np.linalg.norm(o.x[:, 0]) < 2e-5

@@ -80,6 +80,18 @@ def test_p12_fixed_steps_match_oracle():
     assert _rel(_np(r.e), o.e) < 5e-5
 
 
+def test_cab_adm_fixed_steps_match_oracle():
+    # ADM (one FISTA step per outer step) on a cross-and-bouquet dictionary:
+    # iterate parity; on such data it converges far more slowly than PALM
+    # (the oracle is still short of tol 1e-5 after 50000 outer steps here)
+    P = cab_problem(m=300, classes=20, per_class=7, N=6, frac=0.3, cfg=213)
+    pl = _plan(P.A, structure="cab", precision="fp32", max_batch=6, max_inner=1)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-50)
+    o = oracle_palm(P.A, P.b, structure="cab", fixed_outer=50, fixed_inner=1)
+    assert _rel(_np(r.x), o.x) < 5e-5
+    assert _rel(_np(r.e), o.e) < 5e-5
+
+
 def test_dense_p1_converged_matches_lp():
     P = dense_p1(trial=2, N=2)
     pl = _plan(P.A, max_batch=2, max_inner=200, xi_growth=1.2)
