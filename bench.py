@@ -250,6 +250,16 @@ def main():
     out["recognition"] = {"rate": rate, "ms": round(cls_ms, 3), "subjects": int(len(ptr) - 1),
                           "score_median": float(score.median())}
     log(f"recognition (Sec. VI-B criterion): {100 * rate:.1f} % of {N} in {cls_ms:.2f} ms")
+    # the residual rule of the classifier the paper builds on, on the same batch
+    from paper_1007_3753_amd import class_residuals
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, rlabel = class_residuals(A, r.x, b, ptr, e=r.e)
+    torch.cuda.synchronize()
+    res_ms = 1e3 * (time.perf_counter() - t)
+    rrate = float((rlabel.cpu().numpy() == P.labels).mean())
+    out["recognition"]["residual_rule"] = {"rate": rrate, "ms": round(res_ms, 3)}
+    log(f"recognition (residual rule): {100 * rrate:.1f} % of {N} in {res_ms:.2f} ms")
     if not args.no_check and args.check_instances > 0:
         from oracle import p1_lp, full_matrix
         Af = full_matrix(P.A, "cab")

@@ -201,6 +201,25 @@ int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n);
 int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* class_ptr_dev,
                     int C, float* mass_dev, int* label_dev, float* score_dev, void* stream);
 
+/* The residual rule of the sparse-representation classifier the paper
+ * builds on (Sec. I; the cross-and-bouquet model b = A x + e of Sec. II-A):
+ * for instance j and subject i (owning columns class_ptr[i] ..
+ * class_ptr[i+1]-1 of A, with the clamping rules of l1_alm_classify)
+ *   res_dev[i + C*j] = ||b_j - e_j - A delta_i(x_j)||_2      (FP32; may be NULL)
+ *   label_dev[j]     = argmin_i res (the lowest i among equal residuals)
+ * A_dev: m x n_dict column-major (leading dimension lda), the dictionary of
+ * the solve (B for the cross-and-bouquet form); x_dev: n_dict x N (ldx);
+ * e_dev: m x N (lde), or NULL for e = 0; b_dev: m x N (ldb).  Every sum is
+ * formed in FP64 from the FP32 inputs in a fixed order, so the residuals
+ * are reproducible and the label is decided in FP64.  Device buffers owned
+ * by the caller; asynchronous on `stream`; needs no plan.
+ * Errors: L1_EINVAL for N < 0, m or n_dict < 1, a leading dimension below
+ * its row count, C outside [2, L1_CLASSIFY_MAX_SUBJECTS] or a NULL A, x, b,
+ * class_ptr or label.                                                      */
+int l1_alm_class_residuals(const float* A_dev, int m, int n_dict, int lda, const float* x_dev, int ldx,
+                           const float* e_dev, int lde, const float* b_dev, int ldb, int N,
+                           const int* class_ptr_dev, int C, float* res_dev, int* label_dev, void* stream);
+
 /* The l1 problem of the alignment step (Sec. II-B, the linearised
  * registration problem; Sec. VI-C):  min ||e||_1  s.t.  b_j = B_j w + e,
  * for N instances, each with its own small m x k dictionary B_j (the

@@ -9,7 +9,7 @@ from ._lib import L1Error, LIB_PATH, load  # noqa: F401
 def __getattr__(name):
     # the torch-facing binding is imported lazily so that the C-ABI checks can
     # run without initialising a GPU
-    if name in ("Plan", "SolveResult", "DALMUnrolled", "classify", "align"):
+    if name in ("Plan", "SolveResult", "DALMUnrolled", "classify", "class_residuals", "align"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -189,6 +189,29 @@ def classify(x, class_ptr):
     return mass.t(), label, score
 
 
+def class_residuals(A, x, b, class_ptr, e=None):
+    """The residual rule of the sparse-representation classifier (Sec. I,
+    Sec. II-A) on the GPU: ``A`` (m, n_dict) the dictionary, ``x``
+    (n_dict, N), ``b`` (m, N), ``e`` (m, N) or None, ``class_ptr`` (C + 1,).
+    Returns (res (C, N), label (N,)) from l1_alm_class_residuals."""
+    lib = _lib.load()
+    A = torch.as_tensor(A)
+    m, n_dict = int(A.shape[0]), int(A.shape[1])
+    Ac = _colmajor(A, m)
+    xc = _colmajor(x, n_dict)
+    bc = _colmajor(b, m)
+    N = int(xc.shape[0])
+    ec = None if e is None else _colmajor(e, m)
+    ptr = torch.as_tensor(class_ptr, dtype=torch.int32, device=xc.device).contiguous()
+    C = int(ptr.numel()) - 1
+    res = torch.empty(N, C, device=xc.device, dtype=torch.float32)
+    label = torch.empty(N, device=xc.device, dtype=torch.int32)
+    _lib.check(lib.l1_alm_class_residuals(_ptr(Ac), m, n_dict, m, _ptr(xc), n_dict,
+                                          None if ec is None else _ptr(ec), m, _ptr(bc), m, N, _ptr(ptr), C,
+                                          _ptr(res), _ptr(label), _stream()))
+    return res.t(), label
+
+
 def align(B, b, tol=1e-3, max_iter=1000, fixed_iters=None):
     """The l1 problem of the alignment step (Sec. II-B; Sec. VI-C) on the
     GPU: ``B`` (N, m, k) per-instance dictionaries, ``b`` (m, N).  Runs the

@@ -9,6 +9,7 @@
 
 #include "internal.h"
 #include "plan.h"
+#include "readout.h"
 #include "steps.h"
 
 namespace l1 {
@@ -376,6 +377,27 @@ int l1_alm_classify(const float* x_dev, int ldx, int n_dict, int N, const int* c
                "x, class_ptr, label and score must be non-NULL");
     classify(reinterpret_cast<hipStream_t>(stream), x_dev, ldx, n_dict, N, class_ptr_dev, C,
              mass_dev, label_dev, score_dev);
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
+int l1_alm_class_residuals(const float* A_dev, int m, int n_dict, int lda, const float* x_dev, int ldx,
+                           const float* e_dev, int lde, const float* b_dev, int ldb, int N,
+                           const int* class_ptr_dev, int C, float* res_dev, int* label_dev, void* stream) {
+  try {
+    L1_REQUIRE(N >= 0 && m >= 1 && n_dict >= 1, "bad m, n_dict or N");
+    L1_REQUIRE(lda >= m && ldx >= n_dict && ldb >= m && (!e_dev || lde >= m), "bad leading dimension");
+    L1_REQUIRE(C >= 2 && C <= L1_CLASSIFY_MAX_SUBJECTS, "C must be in [2, 4096]");
+    if (N == 0) return L1_OK;
+    L1_REQUIRE(A_dev && x_dev && b_dev && class_ptr_dev && label_dev,
+               "A, x, b, class_ptr and label must be non-NULL");
+    class_residuals(reinterpret_cast<hipStream_t>(stream), A_dev, m, n_dict, lda, x_dev, ldx, e_dev, lde, b_dev,
+                    ldb, N, class_ptr_dev, C, res_dev, label_dev);
     return L1_OK;
   } catch (const Fail& f) {
     return f.code;
