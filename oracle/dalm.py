@@ -78,12 +78,13 @@ class DalmResult:
 
 
 def _dalm_one(Af, b, beta, tol, max_iter, lam, eps, n_dict, problem,
-              w0, y0, fixed, record):
+              w0, y0, fixed, record, y_step="exact"):
     m, n = Af.shape
-    G = Af @ Af.T
-    if problem == "qp":
-        G = G + (lam / beta) * np.eye(m)
-    cf = sl.cho_factor(G, lower=True)
+    if y_step == "exact":
+        G = Af @ Af.T
+        if problem == "qp":
+            G = G + (lam / beta) * np.eye(m)
+        cf = sl.cho_factor(G, lower=True)
     w = np.zeros(n) if w0 is None else np.array(w0, dtype=np.float64)
     y = np.zeros(m) if y0 is None else np.array(y0, dtype=np.float64)
     v = Af.T @ y
@@ -97,7 +98,18 @@ def _dalm_one(Af, b, beta, tol, max_iter, lam, eps, n_dict, problem,
         if problem == "p12":
             z[n_dict:] = block_soft(s[n_dict:], eps / beta)
         # y-step: (A A^T [+ lam/beta I]) y = A z - (A w - b)/beta
-        y = sl.cho_solve(cf, Af @ z - (Af @ w - b) / beta)
+        rhs = Af @ z - (Af @ w - b) / beta
+        if y_step == "exact":
+            y = sl.cho_solve(cf, rhs)
+        else:
+            # one conjugate-gradient step from y_k on the same system (the
+            # heuristic of Sec. V-B): the first CG step is steepest descent
+            # on q(y) = y^T G y / 2 - rhs^T y with the exact step length
+            g = Af @ v + (lam / beta) * y - rhs if problem == "qp" else Af @ v - rhs
+            Atg = Af.T @ g
+            den = Atg @ Atg + ((lam / beta) * (g @ g) if problem == "qp" else 0.0)
+            if den > 0:
+                y = y - (g @ g) / den * g
         v_new = Af.T @ y
         # w-step
         w_new = w - beta * (z - v_new)
@@ -122,8 +134,11 @@ def _dalm_one(Af, b, beta, tol, max_iter, lam, eps, n_dict, problem,
 
 def dalm(A, b, *, structure="dense", problem="p1", beta=None, lam=None, eps=None,
          tol=1e-12, max_iter=100000, fixed_iters: Optional[int] = None,
-         w0=None, y0=None, record=False) -> DalmResult:
+         w0=None, y0=None, record=False, y_step="exact") -> DalmResult:
     """Run DALM on every column of ``b``.
+
+    ``y_step="cg1"`` replaces the exact y-step by one conjugate-gradient step
+    from the current y (the cheaper heuristic mentioned in Sec. V-B).
 
     ``A`` is the dictionary (B for ``structure="cab"``).  ``beta`` is a scalar
     or a per-instance array (default ``||b_j||_1/m``).  ``fixed_iters`` runs
@@ -145,6 +160,8 @@ def dalm(A, b, *, structure="dense", problem="p1", beta=None, lam=None, eps=None
         raise ValueError("QP_lambda is defined on a dense dictionary")
     if problem == "p12" and structure == "cab":
         raise ValueError("P_{1,2} is defined on a dense dictionary")
+    if y_step not in ("exact", "cg1"):
+        raise ValueError("y_step must be 'exact' or 'cg1'")
     betas = np.empty(N)
     for j in range(N):
         if beta is None:
@@ -162,7 +179,7 @@ def dalm(A, b, *, structure="dense", problem="p1", beta=None, lam=None, eps=None
             lam, None if eps_arr is None else eps_arr[j], n_dict, problem,
             None if w0 is None else np.asarray(w0)[:, j],
             None if y0 is None else np.asarray(y0)[:, j],
-            fixed_iters, record)
+            fixed_iters, record, y_step)
         W[:, j], Y[:, j], V[:, j], its[j], st[j] = w, y, v, k, s
         hist.append(h)
     return DalmResult(W, Y, V, its, st, betas, hist)

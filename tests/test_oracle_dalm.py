@@ -169,3 +169,64 @@ def test_synthetic_recipe_recovers_planted():
         assert np.linalg.norm(rd.w[:, 0] - w_lp) < 1e-7 * np.linalg.norm(w_lp)
         rp = palm(A, b, tol=1e-10, max_iter=2000, max_inner=500)
         assert np.linalg.norm(rp.x[:, 0] - w_lp) < 1e-7 * np.linalg.norm(w_lp)
+
+
+# ---- the one-CG-step y-step (the heuristic of Sec. V-B)
+
+def test_cg1_is_exact_when_rows_are_orthogonal():
+    # A A^T = c I: the y-subproblem is spherical, one steepest-descent step with
+    # the exact step length solves it, so the iterates are Algorithm 2's
+    rng = np.random.default_rng(41)
+    Q, _ = np.linalg.qr(rng.standard_normal((90, 90)))
+    A = 1.7 * Q[:30, :]
+    x0 = np.zeros(90)
+    x0[rng.choice(90, 5, replace=False)] = rng.standard_normal(5)
+    b = A @ x0
+    oc = dalm(A, b[:, None], fixed_iters=40, y_step="cg1")
+    oe = dalm(A, b[:, None], fixed_iters=40)
+    np.testing.assert_allclose(oc.w, oe.w, rtol=0, atol=1e-12 * np.abs(oe.w).max())
+    np.testing.assert_allclose(oc.y, oe.y, rtol=0, atol=1e-12 * np.abs(oe.y).max())
+
+
+def test_cg1_step_minimises_the_y_subproblem_along_the_gradient():
+    # one iteration from a given (w, y): the new y is the minimiser of the
+    # y-subproblem's quadratic on the line through y along its gradient
+    from scipy.optimize import minimize_scalar
+    rng = np.random.default_rng(42)
+    A = rng.standard_normal((12, 30))
+    b = rng.standard_normal(12)
+    w0 = rng.standard_normal(30)
+    y0 = rng.standard_normal(12)
+    beta = 0.7
+    o = dalm(A, b[:, None], beta=beta, fixed_iters=1, w0=w0[:, None], y0=y0[:, None], y_step="cg1")
+    z = np.clip(A.T @ y0 + w0 / beta, -1.0, 1.0)
+    G = A @ A.T
+
+    def lagr(y):   # the augmented Lagrangian's y-dependent part (Sec. V-B)
+        return -b @ y - w0 @ (z - A.T @ y) + 0.5 * beta * np.sum((z - A.T @ y) ** 2)
+
+    h = 1e-6
+    grad = np.array([(lagr(y0 + h * e) - lagr(y0 - h * e)) / (2 * h) for e in np.eye(12)])
+    t = minimize_scalar(lambda t: lagr(y0 - t * grad), bracket=(0.0, 1e-3), tol=1e-14).x
+    np.testing.assert_allclose(o.y[:, 0], y0 - t * grad, rtol=1e-6, atol=1e-9)
+    del G
+
+
+def test_cg1_converges_on_gaussian_data_and_not_on_face_shaped_data():
+    # Sec. V-B: the heuristic works on random Gaussian dictionaries but not on
+    # face dictionaries
+    P = dense_p1(m=200, n=600, k=20, N=1, cfg=43)
+    x_lp, _ = p1_lp(P.A, P.b[:, 0])
+    o = dalm(P.A, P.b, tol=1e-6, max_iter=5000, y_step="cg1")
+    assert o.status[0] == 0
+    assert np.linalg.norm(o.w[:, 0] - x_lp) < 1e-5 * np.linalg.norm(x_lp)
+    o = dalm(P.A, P.b, fixed_iters=2000, y_step="cg1")   # to the LP solver's own accuracy
+    assert np.linalg.norm(o.w[:, 0] - x_lp) < 1e-7 * np.linalg.norm(x_lp)
+    C = cab_problem(m=300, classes=20, per_class=7, N=1, frac=0.3, cfg=212)
+    Af = full_matrix(C.A, "cab")
+    w_lp, _ = p1_lp(Af, C.b[:, 0])
+    oc = dalm(C.A, C.b, structure="cab", fixed_iters=3000, y_step="cg1")
+    oe = dalm(C.A, C.b, structure="cab", fixed_iters=3000)
+    err_c = np.linalg.norm(oc.w[:, 0] - w_lp) / np.linalg.norm(w_lp)
+    err_e = np.linalg.norm(oe.w[:, 0] - w_lp) / np.linalg.norm(w_lp)
+    assert err_e < 1e-3 and err_c > 10 * err_e
