@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + sorted(E1_WORKLOADS) + sorted(ALIGN_WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16_refine", "bf16x3"],
                     help="default: bf16_refine (cross-and-bouquet), fp32 (e1-*)")
-    ap.add_argument("--method", default="dalm", choices=["dalm", "palm", "adm"],
+    ap.add_argument("--method", default="dalm", choices=["dalm", "palm", "adm", "dalm_cg1"],
                     help="e1-* workloads only (the cross-and-bouquet benchmark is DALM)")
     ap.add_argument("--e1-instances", type=int, default=20)
     ap.add_argument("--tol", type=float, default=4e-6)
@@ -342,10 +342,11 @@ def e1_main(args):
     nx0 = np.linalg.norm(X0, axis=0)
     # ADM: PALM with one FISTA step per outer step (the inexact form the paper compares with, Sec. V-A)
     inner = 1 if args.method == "adm" else 100
-    plan = Plan(A, structure="dense", method="dalm" if args.method == "dalm" else "palm", precision=prec,
+    plan = Plan(A, structure="dense", method={"adm": "palm"}.get(args.method, args.method), precision=prec,
                 max_batch=N, max_inner=inner, time_kernels=True)
     plan_ms = plan.last_stats()["plan_ms"]
     ks = {"dalm": [5, 10, 20, 30, 50, 70, 100, 150, 200, 300, 500, 1000, 2000],
+          "dalm_cg1": [5, 10, 20, 30, 50, 70, 100, 150, 200, 300, 500, 1000, 2000],
           "palm": [1, 2, 3, 5, 7, 10, 15, 20, 30, 50, 70, 100, 150, 200, 300, 500],
           "adm": [10, 20, 50, 70, 100, 150, 200, 300, 500, 700, 1000, 2000, 5000]}[args.method]
     target = 1e-5
@@ -403,6 +404,16 @@ def e1_main(args):
         nl = agg["timed_launches"]
         bytes_total = nl * n * n * 4 + n * N * nl * 28
         what = "DALM iteration: gemm_kernel<EPI_DALM> (+ split-K part), HIP events"
+    elif args.method == "dalm_cg1" and hit is not None:
+        # wall clock of the fixed-count solve: per iteration A is read twice
+        # (A u and A^T g, FP32) and per instance the model of the three
+        # elementwise launches, n (36) + m (28) bytes
+        kern_s = hit[1] / 1e3
+        nl = hit[0]
+        m_ = wl["m"]
+        bytes_total = nl * (8 * m_ * n + N * (36 * n + 28 * m_))
+        what = ("DALM with one CG step: two FP32 products (A u, A^T g) and three elementwise launches per "
+                "iteration, wall clock of the whole solve")
     elif args.method in ("palm", "adm") and hit is not None:
         # wall clock of the fixed-count solve (no per-launch events on this
         # path): K outer steps of `inner` FISTA steps, each the Gram matrix
@@ -427,6 +438,8 @@ def e1_main(args):
         t = time.perf_counter()
         if args.method == "dalm":
             oracle_dalm(P.A, P.b[:, :1], structure="dense", fixed_iters=hit[0])
+        elif args.method == "dalm_cg1":
+            oracle_dalm(P.A, P.b[:, :1], structure="dense", fixed_iters=hit[0], y_step="cg1")
         else:
             oracle_palm(P.A, P.b[:, :1], structure="dense", fixed_outer=hit[0], fixed_inner=inner)
         dt = time.perf_counter() - t

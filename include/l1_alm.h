@@ -51,7 +51,13 @@ extern "C" {
 
 typedef enum { L1_P1 = 0, L1_P12 = 1, L1_QPLAMBDA = 2 } l1_problem;
 typedef enum { L1_DENSE = 0, L1_CAB = 1 } l1_structure;
-typedef enum { L1_DALM = 0, L1_PALM = 1 } l1_method;
+/* L1_DALM_CG1: DALM with the y-step replaced by one conjugate-gradient step
+ * from the current y (the cheaper heuristic of Sec. V-B, which the paper
+ * reports to work on random Gaussian dictionaries but not on face
+ * dictionaries).  Builds no inverse; per iteration two FP32 products, A u
+ * and A^T g.  (P1) only, dense or cross-and-bouquet, L1_FP32 only; same
+ * stopping test, beta default and outputs as L1_DALM; no warm start.      */
+typedef enum { L1_DALM = 0, L1_PALM = 1, L1_DALM_CG1 = 2 } l1_method;
 /* Arithmetic of the per-iteration matrix products.  State, elementwise
  * updates and accumulation are FP32 in every mode; the operator is rounded
  * from FP64 once per plan.

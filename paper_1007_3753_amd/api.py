@@ -13,7 +13,7 @@ from . import _lib
 
 PROBLEMS = {"p1": 0, "p12": 1, "qp": 2}
 STRUCTURES = {"dense": 0, "cab": 1}
-METHODS = {"dalm": 0, "palm": 1}
+METHODS = {"dalm": 0, "palm": 1, "dalm_cg1": 2}
 PRECISIONS = {"fp32": 0, "bf16_refine": 1, "bf16x3": 2}
 CONVERGED, MAXITER, NONFINITE = 0, 1, 2
 
@@ -108,7 +108,7 @@ class Plan:
         x = torch.empty(N, self.n_dict, device=dev, dtype=torch.float32)
         has_e = self.split or (self.method == "palm" and self.problem == "qp")
         e = torch.empty(N, self.m, device=dev, dtype=torch.float32) if has_e else None
-        y = torch.empty(N, self.m, device=dev, dtype=torch.float32) if (want_y and self.method == "dalm") else None
+        y = torch.empty(N, self.m, device=dev, dtype=torch.float32) if (want_y and self.method in ("dalm", "dalm_cg1")) else None
         iters = torch.empty(N, device=dev, dtype=torch.int32)
         status = torch.empty(N, device=dev, dtype=torch.int32)
         epsc = None

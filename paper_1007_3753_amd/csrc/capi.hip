@@ -152,7 +152,9 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   L1_REQUIRE(d->max_batch >= 1, "max_batch must be >= 1");
   L1_REQUIRE(d->problem >= 0 && d->problem <= 2, "unknown problem");
   L1_REQUIRE(d->structure == L1_DENSE || d->structure == L1_CAB, "unknown structure");
-  L1_REQUIRE(d->method == L1_DALM || d->method == L1_PALM, "unknown method");
+  L1_REQUIRE(d->method == L1_DALM || d->method == L1_PALM || d->method == L1_DALM_CG1, "unknown method");
+  L1_REQUIRE(d->method != L1_DALM_CG1 || (d->problem == L1_P1 && d->precision == L1_FP32),
+             "L1_DALM_CG1 runs (P1) with L1_FP32 products");
   L1_REQUIRE(d->precision >= 0 && d->precision <= 2, "unknown precision");
   L1_REQUIRE(!(d->structure == L1_CAB && d->problem != L1_P1),
              "QP_lambda and P_{1,2} are defined on a dense dictionary (structure L1_DENSE)");
@@ -219,7 +221,7 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
       L1_HIP(hipMemsetAsync(p->Yop, 0, sizeof(float) * p->m_pad * p->n_pad, s));
     }
     build_dalm(p.get(), s, A64, sc, info);
-  } else {
+  } else if (d->method == L1_PALM) {
     const size_t nn = (size_t)p->nd_pad * p->nd_pad;
     p->M32 = dalloc<float>(nn, o);
     L1_HIP(hipMemsetAsync(p->M32, 0, sizeof(float) * nn, s));
@@ -234,7 +236,7 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
 
   // per-solve workspace
   const size_t Np = p->N_pad;
-  const int rows = (d->method == L1_DALM) ? p->n_pad : std::max(p->nd_pad, p->m_pad);
+  const int rows = (d->method != L1_PALM) ? p->n_pad : std::max(p->nd_pad, p->m_pad);
   p->lds = rows;
   const size_t st = (size_t)rows * Np;
   p->W = dalloc<float>(st, o);
@@ -328,7 +330,8 @@ int l1_alm_solve(l1_alm_plan_t plan, const float* b_dev, int ldb, int N, const f
     SolveArgs a{b_dev, ldb, N, eps_dev, tol, max_iter, w0_dev, y0_dev, x_dev, ldx, e_dev, lde,
                 y_dev, ldy, iters_dev, status_dev, reinterpret_cast<hipStream_t>(stream)};
     if (p->d.method == L1_DALM) solve_dalm(p, a);
-    else solve_palm(p, a);
+    else if (p->d.method == L1_PALM) solve_palm(p, a);
+    else solve_dalm_cg1(p, a);
     return L1_OK;
   } catch (const Fail& f) {
     return f.code;

@@ -85,6 +85,8 @@ void solve_dalm(Plan* p, const SolveArgs& a);
 // over `phases_used` precision phases (1 = no split)
 int dalm_ksplit(const Plan* p, int active, int phases_used);
 void solve_palm(Plan* p, const SolveArgs& a);
+// DALM with one conjugate-gradient step for the y-step (csrc/cg1.hip)
+void solve_dalm_cg1(Plan* p, const SolveArgs& a);
 void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* gA,
                    hipStream_t s);
 
