@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--cpu-instances", type=int, default=4,
                     help="instances the FP64 CPU oracle solves for the cpu_baseline figure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the split-K autotuner on the plan before timing and record it in the cache")
+    ap.add_argument("--tune-out", default=None, help="cache file written by --tune (default: the package's)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -135,6 +138,18 @@ def main():
     plan = Plan(A, structure="cab", precision=args.precision, max_batch=N, time_kernels=True)
     plan_ms = plan.last_stats()["plan_ms"]
     log(f"plan ({args.precision}) built in {plan_ms:.1f} ms")
+    # launch shape: the split-K table from the autotuner (run here with
+    # --tune, before the timed region), else the cached one, else the heuristic
+    from paper_1007_3753_amd import tuning
+    if args.tune:
+        t0 = time.perf_counter()
+        table = tuning.tune(plan, path=args.tune_out or tuning.CACHE)
+        ks_info = {"source": "tuned in this run", "table": table,
+                   "tune_s": round(time.perf_counter() - t0, 2)}
+    else:
+        table = tuning.apply(plan)
+        ks_info = {"source": "cache" if table is not None else "heuristic", "table": table}
+    log(f"split-K table: {ks_info}")
 
     def step():
         r = plan.solve(b, tol=args.tol, max_iter=args.max_iter)
@@ -221,6 +236,7 @@ def main():
                    "problem": "P1", "structure": "cab", "method": "dalm",
                    "precision": args.precision, "tol": args.tol, "max_iter": args.max_iter},
         "plan_ms": round(plan_ms, 2),
+        "ksplit": ks_info,
         "iterations": {"mean": float(iters.mean()), "max": int(iters.max())},
         "status_counts": np.bincount(status, minlength=3).tolist(),
         "kkt_max": {"primal": float(rep[:, 0].max()), "dual_inf": float(rep[:, 1].max()),

@@ -185,6 +185,31 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
  * BF16 4e-6 (the level where rounding noise stalls the test).             */
 int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n);
 
+/* Launch shape of the DALM iteration product.  When few instances are
+ * active the product's K range is split over 1..L1_KSPLIT_MAX workgroups per
+ * output tile (a second launch adds the parts).  By default the number of
+ * parts comes from a heuristic (enough workgroups for the device); a table
+ * indexed by the number of active 64-instance column tiles t = 1..n
+ * (n <= L1_KSPLIT_TILES) replaces it: ks_by_tiles[t - 1] parts, 0 = keep the
+ * heuristic for that t.  The table is part of the plan and persists until
+ * set again (n = 0 clears it).  Errors: L1_EINVAL for a NULL plan, n outside
+ * [0, L1_KSPLIT_TILES] or an entry outside [0, L1_KSPLIT_MAX].            */
+#define L1_KSPLIT_TILES 8
+#define L1_KSPLIT_MAX 4
+int l1_alm_set_ksplit(l1_alm_plan_t plan, const int* ks_by_tiles, int n);
+
+/* Autotuner of that table for a DALM plan: for t = 2 .. min(L1_KSPLIT_TILES,
+ * max_batch / 64) it times fixed-count solves of t * 64 synthetic right-hand
+ * sides (`iters` iterations each, median of 3, HIP events on `stream`) for
+ * every split 1..L1_KSPLIT_MAX, keeps the fastest in the plan and writes the
+ * table (n entries, t = 1..n; entry 1 stays 0: with one active column tile
+ * the tail kernel takes over and uses the heuristic's split) to ks_out (host
+ * memory).  The timings run in the plan's first arithmetic (BF16 for
+ * L1_BF16_REFINE).  Allocates and frees its own device buffers; the solve
+ * workspace of the plan is overwritten.  Errors: L1_EINVAL for a non-DALM or
+ * (P1,2) plan, iters outside [16, 4096] or a bad n.                        */
+int l1_alm_tune_ksplit(l1_alm_plan_t plan, int iters, int* ks_out, int n, void* stream);
+
 /* The recognition criterion of the face experiments (Sec. VI-B), applied to
  * N representations x (n_dict x N, column-major, ld ldx >= n_dict) of test
  * vectors over a dictionary whose columns are grouped by subject: subject i

@@ -13,7 +13,7 @@ L1_OK, L1_EINVAL, L1_ENOTSPD, L1_ENOMEM, L1_EHIP, L1_ENODEVICE, L1_ENOTAPE = 0, 
 ERROR_NAMES = {L1_EINVAL: "L1_EINVAL", L1_ENOTSPD: "L1_ENOTSPD", L1_ENOMEM: "L1_ENOMEM",
                L1_EHIP: "L1_EHIP", L1_ENODEVICE: "L1_ENODEVICE", L1_ENOTAPE: "L1_ENOTAPE"}
 EXPORTED = ("l1_alm_plan", "l1_alm_solve", "l1_alm_backward", "l1_alm_kkt", "l1_alm_classify",
-            "l1_alm_class_residuals", "l1_alm_align", "l1_alm_last_stats", "l1_alm_destroy", "l1_alm_last_error")
+            "l1_alm_class_residuals", "l1_alm_align", "l1_alm_set_ksplit", "l1_alm_tune_ksplit", "l1_alm_last_stats", "l1_alm_destroy", "l1_alm_last_error")
 
 
 class l1_alm_desc(ctypes.Structure):
@@ -53,6 +53,8 @@ def load(path=LIB_PATH):
     lib.l1_alm_kkt.argtypes = [vp, vp, i, i, vp, vp, i, vp, i, vp, i, vp, vp]
     lib.l1_alm_classify.argtypes = [vp, i, i, i, vp, i, vp, vp, vp, vp]
     lib.l1_alm_class_residuals.argtypes = [vp, i, i, i, vp, i, vp, i, vp, i, i, vp, i, vp, vp, vp]
+    lib.l1_alm_set_ksplit.argtypes = [vp, vp, i]
+    lib.l1_alm_tune_ksplit.argtypes = [vp, i, vp, i, vp]
     lib.l1_alm_align.argtypes = [vp, i, i, i, vp, i, f, i, vp, vp, i, vp, vp, vp]
     lib.l1_alm_last_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i]
     lib.l1_alm_destroy.argtypes = [vp]

@@ -127,6 +127,19 @@ class Plan:
         return SolveResult(x.t(), None if e is None else e.t(), None if y is None else y.t(),
                            iters, status)
 
+    def set_ksplit(self, table):
+        """Install a split-K table (parts by active 64-instance column tiles
+        1..len(table); 0 keeps the heuristic); an empty table clears it."""
+        t = (ctypes.c_int * max(len(table), 1))(*[int(v) for v in table])
+        _lib.check(self.lib.l1_alm_set_ksplit(self.handle, t, len(table)))
+
+    def tune_ksplit(self, iters=256):
+        """Run the split-K autotuner of l1_alm_tune_ksplit on this plan and
+        return the table it installed (8 entries)."""
+        out = (ctypes.c_int * 8)()
+        _lib.check(self.lib.l1_alm_tune_ksplit(self.handle, int(iters), out, 8, _stream()))
+        return list(out)
+
     def backward(self, gx, ge=None):
         """Reverse-mode product of the last recorded fixed-count solve: given
         the adjoints of its outputs x (n_dict, N) and e (m, N), returns

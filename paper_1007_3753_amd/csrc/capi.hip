@@ -434,6 +434,105 @@ int l1_alm_align(const float* B_dev, int m, int k, int N, const float* b_dev, in
   }
 }
 
+int l1_alm_set_ksplit(l1_alm_plan_t plan, const int* ks_by_tiles, int n) {
+  try {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    L1_REQUIRE(p != nullptr, "plan is NULL");
+    L1_REQUIRE(n >= 0 && n <= L1_KSPLIT_TILES && (n == 0 || ks_by_tiles != nullptr), "bad table");
+    for (int i = 0; i < n; ++i)
+      L1_REQUIRE(ks_by_tiles[i] >= 0 && ks_by_tiles[i] <= L1_KSPLIT_MAX, "split-K parts must be in [0, 4]");
+    for (int t = 1; t <= L1_KSPLIT_TILES; ++t) p->ks_table[t] = t <= n ? ks_by_tiles[t - 1] : 0;
+    return L1_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
+int l1_alm_tune_ksplit(l1_alm_plan_t plan, int iters, int* ks_out, int n, void* stream) {
+  float* b = nullptr;
+  float* x = nullptr;
+  int* it = nullptr;
+  int* st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    if (b) (void)hipFree(b);
+    if (x) (void)hipFree(x);
+    if (it) (void)hipFree(it);
+    if (st) (void)hipFree(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  try {
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    L1_REQUIRE(p != nullptr, "plan is NULL");
+    L1_REQUIRE(p->d.method == L1_DALM, "the split-K table belongs to the DALM iteration");
+    L1_REQUIRE(iters >= 16 && iters <= 4096, "iters must be in [16, 4096]");
+    L1_REQUIRE(n >= 0 && n <= L1_KSPLIT_TILES && (n == 0 || ks_out != nullptr), "bad table");
+    L1_REQUIRE(p->d.problem != L1_P12, "tuning runs (P1) and (QP_lambda) plans");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int m = p->m, nd = std::max(p->nd, 1);
+    const int tmax = std::min(L1_KSPLIT_TILES, p->d.max_batch / TILE);
+    const int Nmax = std::max(tmax, 1) * TILE;
+    // synthetic right-hand sides: U[0, 1) entries (the timing of a fixed
+    // count of iterations does not depend on the values)
+    std::vector<float> hb((size_t)m * Nmax);
+    unsigned long long r = 0x9E3779B97F4A7C15ull;
+    for (auto& v : hb) {
+      r ^= r << 13;
+      r ^= r >> 7;
+      r ^= r << 17;
+      v = (float)((r >> 40) & 0xFFFFFF) / 16777216.0f;
+    }
+    L1_HIP(hipMalloc((void**)&b, sizeof(float) * hb.size()));
+    L1_HIP(hipMalloc((void**)&x, sizeof(float) * (size_t)nd * Nmax));
+    L1_HIP(hipMalloc((void**)&it, sizeof(int) * Nmax));
+    L1_HIP(hipMalloc((void**)&st, sizeof(int) * Nmax));
+    L1_HIP(hipMemcpyAsync(b, hb.data(), sizeof(float) * hb.size(), hipMemcpyHostToDevice, s));
+    L1_HIP(hipEventCreate(&e0));
+    L1_HIP(hipEventCreate(&e1));
+    // one active column tile stays with the heuristic: the tail kernel
+    // takes over there and runs the parts the heuristic gives it
+    for (int t = 2; t <= tmax; ++t) {
+      const int N = t * TILE;
+      SolveArgs a{b, m, N, nullptr, 0.0f, -iters, nullptr, nullptr, x, nd, nullptr, 0,
+                  nullptr, 0, it, st, s};
+      float best = 0.0f;
+      int best_ks = 0;
+      for (int ks = 1; ks <= L1_KSPLIT_MAX; ++ks) {
+        p->ks_table[t] = ks;
+        solve_dalm(p, a);   // warm-up (graphs, code objects)
+        float ms[3];
+        for (int rep = 0; rep < 3; ++rep) {
+          L1_HIP(hipEventRecord(e0, s));
+          solve_dalm(p, a);
+          L1_HIP(hipEventRecord(e1, s));
+          L1_HIP(hipEventSynchronize(e1));
+          L1_HIP(hipEventElapsedTime(&ms[rep], e0, e1));
+        }
+        std::sort(ms, ms + 3);
+        if (best_ks == 0 || ms[1] < best) {
+          best = ms[1];
+          best_ks = ks;
+        }
+      }
+      p->ks_table[t] = best_ks;
+    }
+    for (int t = 1; t <= n; ++t) ks_out[t - 1] = p->ks_table[t];
+    release();
+    return L1_OK;
+  } catch (const Fail& f) {
+    release();
+    return f.code;
+  } catch (const std::exception& e) {
+    release();
+    set_error(e.what());
+    return L1_EHIP;
+  }
+}
+
 int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n) {
   try {
     Plan* p = reinterpret_cast<Plan*>(plan);

@@ -45,6 +45,9 @@ struct Plan {
   float* partial = nullptr;
   float* ws = nullptr;    // split-K workspace: ws_tiles x TILE x lds floats
   int ws_tiles = 0, ks_target = 192, ks_max = 4;
+  // split-K parts of the DALM iteration product by the number of active
+  // 64-instance column tiles (index 1..8); 0 = the heuristic (dalm_ksplit)
+  int ks_table[9] = {0};
   int* ints = nullptr;    // lists and counters
   long long* stat = nullptr;
   double* kkt_rbuf = nullptr;

@@ -87,6 +87,9 @@ int dalm_ksplit(const Plan* p, int active, int phases_used) {
   const int est = (active + TILE - 1) / TILE + phases_used - 1;
   // split only when the launch would leave most compute units idle
   int ks = (RT * est >= p->ks_target) ? 1 : (p->ks_target + RT * est - 1) / (RT * est);
+  // a tuned choice for this many active column tiles replaces the heuristic
+  const int at = (active + TILE - 1) / TILE;
+  if (at >= 1 && at <= 8 && p->ks_table[at] > 0) ks = p->ks_table[at];
   ks = std::min({ks, p->ks_max, nk64, std::max(1, p->ws_tiles / ctiles)});
   return std::max(ks, 1);
 }

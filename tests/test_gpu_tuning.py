@@ -1,0 +1,79 @@
+"""The split-K autotuner of the DALM iteration (l1_alm_tune_ksplit) and the
+table that replaces the launch-shape heuristic (l1_alm_set_ksplit): the
+tuner returns a valid table, and a solve under any table reaches the same
+iterates as the oracle (the split changes only the order of the K sums)."""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import dalm as oracle_dalm
+from workloads import cab_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _plan(P, **kw):
+    from paper_1007_3753_amd import Plan
+    return Plan(torch.as_tensor(P.A, device="cuda"), structure="cab", **kw)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_tuner_returns_a_valid_table(tmp_path):
+    from paper_1007_3753_amd import tuning
+    P = cab_problem(m=300, classes=20, per_class=7, N=256, frac=0.3, cfg=61)
+    pl = _plan(P, precision="bf16_refine", max_batch=256)
+    table = tuning.tune(pl, iters=32, path=str(tmp_path / "ks.json"))
+    assert len(table) == 8 and table[0] == 0
+    assert all(1 <= t <= 4 for t in table[1:4]) and all(t == 0 for t in table[4:])
+    assert tuning.lookup(pl, str(tmp_path / "ks.json")) == table
+    rec = json.load(open(tmp_path / "ks.json"))
+    assert list(rec.values())[0]["ksplit"] == table
+
+
+@pytest.mark.parametrize("ks", [1, 2, 3, 4])
+def test_any_table_gives_the_oracle_iterates(ks):
+    # 130 instances: 3 active column tiles, so entry 3 of the table decides the split
+    P = cab_problem(m=300, classes=20, per_class=7, N=130, frac=0.3, cfg=62)
+    pl = _plan(P, precision="fp32", max_batch=130)
+    pl.set_ksplit([0, ks, ks, ks])
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-30)
+    cols = [0, 64, 129]
+    o = oracle_dalm(P.A, P.b[:, cols], structure="cab", fixed_iters=30)
+    x = r.x.cpu().numpy().astype(np.float64)[:, cols]
+    assert _rel(x, o.w[:P.A.shape[1]]) < 5e-5
+    # the same table gives the same bits
+    r2 = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-30)
+    assert torch.equal(r.x, r2.x)
+
+
+def test_tuned_plan_solves_to_tolerance():
+    from paper_1007_3753_amd import tuning
+    P = cab_problem(m=300, classes=20, per_class=7, N=200, frac=0.3, cfg=63)
+    pl = _plan(P, precision="bf16_refine", max_batch=200)
+    table = pl.tune_ksplit(32)
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), tol=4e-6, max_iter=40000)
+    assert np.all(r.status.cpu().numpy() == 0)
+    x = r.x.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(x - P.x0, axis=0) / np.linalg.norm(P.x0, axis=0)
+    assert err.max() < 1e-3
+    del table, tuning
+
+
+def test_bad_tables_are_rejected():
+    from paper_1007_3753_amd import L1Error
+    P = cab_problem(m=130, classes=7, per_class=7, N=8, frac=0.3, cfg=64)
+    pl = _plan(P, precision="fp32", max_batch=8)
+    with pytest.raises(L1Error):
+        pl.set_ksplit([0, 5])
+    with pytest.raises(L1Error):
+        pl.set_ksplit([0] * 9)
+    pl.set_ksplit([])
+    from paper_1007_3753_amd import Plan
+    palm = Plan(torch.as_tensor(P.A, device="cuda"), structure="cab", method="palm", max_batch=8)
+    with pytest.raises(L1Error):
+        palm.tune_ksplit(32)
