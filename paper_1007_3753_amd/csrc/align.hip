@@ -69,11 +69,13 @@ __global__ __launch_bounds__(AL_THREADS) void align_kernel(const float* Bg, int 
                                                            float* wg, float* eg, int lde, int* iters,
                                                            int* status) {
   __shared__ double s_red[16];
-  // rows of B on their way to the matrix cores and the waves' partial Gram
-  // matrices (set-up), then the threads' partial B^T s (iterations; rows
-  // padded by 16 floats so that the segment sums read without bank conflicts)
+  // rows of B on their way to the matrix cores (a row per thread, padded to
+  // 17 floats so that the threads' row writes fall in different banks) and
+  // the waves' partial Gram matrices (set-up), then the threads' partial
+  // B^T s (iterations; rows padded by 16 floats so that the segment sums
+  // read without bank conflicts)
   __shared__ union {
-    float chunk[AL_THREADS][16];
+    float chunk[AL_THREADS][17];
     double gw[4][16][16];
     float p[KP][AL_THREADS + 16];
   } s_u;
