@@ -13,7 +13,7 @@ full matrix [B, I] and w = [x; e].  The y-step uses a Cholesky factor of the
 Gram matrix (``scipy.linalg.cho_factor``/``cho_solve``); the paper applies
 the inverse directly, which is the same solve.
 
-Readings of points the paper leaves open (each is listed in the design doc):
+Readings of points the paper leaves open:
 
 * Algorithm 2 writes the face dictionary in steps 4 and 5; the dimensions only
   agree with the full matrix [B, I], which is what runs here.

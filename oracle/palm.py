@@ -15,7 +15,7 @@ updated separately (eq. (alm-CAB), Algorithm 1):
 
 with inputs x_1 = 0, e_1 = b, theta_1 = 0 and ``xi = 2m/||b||_1``.
 
-Readings (listed in DESIGN.md):
+Readings of points the paper leaves open:
 
 * L, used but not defined in Algorithm 1, is the Lipschitz constant of the
   FISTA gradient, ``||A^T A||_2`` for the dictionary the x-block multiplies.
