@@ -192,3 +192,22 @@ def test_tail_kernel_reproduces_launch_path(precision, monkeypatch):
     assert torch.equal(fixed_tail.x, fixed_loop.x) and torch.equal(fixed_tail.e, fixed_loop.e)
     assert torch.equal(tol_tail.x, tol_loop.x)
     assert torch.equal(tol_tail.iters, tol_loop.iters) and torch.equal(tol_tail.status, tol_loop.status)
+
+
+@pytest.mark.parametrize("N", [12, 16])
+def test_tail_kernel_at_full_operator_size(N, monkeypatch):
+    # 1200 x 700 cross-and-bouquet (n_pad 1920): the instances run one launch
+    # per iteration until at most 6 are left, then the tail kernel runs the
+    # rest; it reproduces the launch-per-iteration path bit for bit
+    P = cab_problem(m=1200, classes=100, per_class=7, N=N, frac=0.3, cfg=208)
+    pl = _plan(P.A, structure="cab", precision="bf16_refine", max_batch=N)
+    b = torch.as_tensor(P.b, device="cuda")
+    fixed_tail = pl.solve(b, max_iter=-300)
+    tol_tail = pl.solve(b, tol=4e-6, max_iter=40000)
+    monkeypatch.setenv("L1ALM_TAIL", "0")
+    fixed_loop = pl.solve(b, max_iter=-300)
+    tol_loop = pl.solve(b, tol=4e-6, max_iter=40000)
+    assert torch.equal(fixed_tail.x, fixed_loop.x) and torch.equal(fixed_tail.e, fixed_loop.e)
+    assert torch.equal(tol_tail.x, tol_loop.x)
+    assert torch.equal(tol_tail.iters, tol_loop.iters) and torch.equal(tol_tail.status, tol_loop.status)
+    assert np.all(tol_tail.status.cpu().numpy() == 0)
