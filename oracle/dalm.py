@@ -37,7 +37,10 @@ Readings of points the paper leaves open:
 
 Parity pins: tests/test_oracle_dalm.py (the first iterate equals the
 minimum-norm solution, the exact plateau formula, LP optimum, brute force,
-KKT certificates, QP_lambda -> P1 as lambda -> 0, P_{1,2} <-> QP_lambda).
+KKT certificates, QP_lambda -> P1 as lambda -> 0, P_{1,2} <-> QP_lambda;
+the one-CG-step y-step: Algorithm 2's iterates when A A^T = cI, its step is
+the line minimiser of the augmented Lagrangian, LP optimum on Gaussian data
+and no convergence in 3000 iterations on face-shaped data).
 """
 from dataclasses import dataclass, field
 from typing import Optional

@@ -211,3 +211,32 @@ def test_tail_kernel_at_full_operator_size(N, monkeypatch):
     assert torch.equal(tol_tail.x, tol_loop.x)
     assert torch.equal(tol_tail.iters, tol_loop.iters) and torch.equal(tol_tail.status, tol_loop.status)
     assert np.all(tol_tail.status.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("structure", ["dense", "cab"])
+def test_warm_start_continues_the_iteration(structure):
+    # Algorithm 2 from a given (w, y): 12 iterations from the oracle's state
+    # after 8 equal 20 iterations from zero
+    if structure == "dense":
+        P = tiny_dense(40, 130, N=4, key=31)
+    else:
+        P = cab_problem(m=130, classes=7, per_class=7, N=4, cfg=209)
+    pl = _plan(P.A, structure=structure, max_batch=4)
+    o8 = oracle_dalm(P.A, P.b, structure=structure, fixed_iters=8)
+    o20 = oracle_dalm(P.A, P.b, structure=structure, fixed_iters=20)
+    dev = "cuda"
+    r = pl.solve(torch.as_tensor(P.b, device=dev), max_iter=-12,
+                 w0=torch.as_tensor(o8.w.astype(np.float32), device=dev),
+                 y0=torch.as_tensor(o8.y.astype(np.float32), device=dev))
+    nd = P.A.shape[1]
+    assert _rel(_np(r.x), o20.w[:nd]) < 5e-5
+    if structure == "cab":
+        assert _rel(_np(r.e), o20.w[nd:]) < 5e-5
+    assert _rel(_np(r.y), o20.y) < 5e-5
+
+
+def test_empty_batch():
+    P = tiny_dense(20, 50, N=1, key=32)
+    pl = _plan(P.A, max_batch=4)
+    r = pl.solve(torch.zeros(20, 0, device="cuda"), tol=1e-6, max_iter=100)
+    assert r.x.shape == (50, 0) and r.iters.numel() == 0
