@@ -49,6 +49,15 @@ ALIGN_WORKLOADS = {
     "align-1200x11-n1000": dict(h=40, wd=30, n_img=7, N=1000, cfg=6, tols=(1e-2, 1e-3, 1e-4), tol=1e-3),
 }
 
+# The (QP_lambda) compressive-sensing sweep: Gaussian 2000 x 8000 with unit
+# columns, 200 +-1 spikes, noise 0.01, lambda = 1e-3, 64 instances sharing A;
+# batched against one instance per launch.
+QP_WORKLOADS = {"qp-2000x8000-n64": dict(tol=3e-6, max_iter=30000, plain=2)}
+# The differentiable unrolled DALM: the 1200 x 700 cross-and-bouquet
+# dictionary, 256 corrupted test vectors, 50 iterations, checkpoints every 10,
+# forward and backward to b and B.
+UNROLLED_WORKLOADS = {"unrolled-1200x700-n256": dict(N=256, iters=50, every=10, cfg=5)}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -59,7 +68,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + sorted(E1_WORKLOADS) + sorted(ALIGN_WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + sorted(E1_WORKLOADS) + sorted(ALIGN_WORKLOADS)
+                    + sorted(QP_WORKLOADS) + sorted(UNROLLED_WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16_refine", "bf16x3"],
                     help="default: bf16_refine (cross-and-bouquet), fp32 (e1-*)")
     ap.add_argument("--method", default="dalm", choices=["dalm", "palm", "adm", "dalm_cg1"],
@@ -114,6 +124,10 @@ def main():
         return e1_main(args)
     if args.workload in ALIGN_WORKLOADS:
         return align_main(args)
+    if args.workload in QP_WORKLOADS:
+        return qp_main(args)
+    if args.workload in UNROLLED_WORKLOADS:
+        return unrolled_main(args)
     if args.precision is None:
         args.precision = "bf16_refine"
     if args.method != "dalm":
@@ -562,6 +576,179 @@ def align_main(args):
             y.copy_(x)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = x.numel() * 4
+    print(json.dumps(out), flush=True)
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:
+        return os.cpu_count()
+
+
+def qp_main(args):
+    """(QP_lambda) sweep: batched DALM solves/s against one instance per
+    launch, accuracy against the oracle's FP64 optimum of instance 0."""
+    import numpy as np
+    import torch
+
+    from paper_1007_3753_amd import Plan
+    from workloads import dense_qp
+
+    wl = QP_WORKLOADS[args.workload]
+    P = dense_qp()
+    N, m, n = P.N, P.m, P.n_dict
+    dev = torch.device("cuda:0")
+    A = torch.as_tensor(P.A, device=dev)
+    b = torch.as_tensor(P.b, device=dev)
+    beta = float(np.mean(np.abs(P.b.astype(np.float64)).sum(0) / m))   # one beta: it enters the factor
+    plan = Plan(A, problem="qp", lam=P.lam, beta=beta, precision="fp32", max_batch=N, time_kernels=True)
+    plan_ms = plan.last_stats()["plan_ms"]
+    for _ in range(args.warmup):
+        plan.solve(b, tol=wl["tol"], max_iter=wl["max_iter"])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    timed_ms = timed_n = 0.0
+    for _ in range(args.steps):
+        r = plan.solve(b, tol=wl["tol"], max_iter=wl["max_iter"])
+        st = plan.last_stats()
+        timed_ms += st["timed_ms"]
+        timed_n += st["timed_launches"]
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / args.steps
+    its = r.iters.cpu().numpy()
+    X = r.x.cpu().numpy().astype(np.float64)
+    rep = plan.kkt(b, r.x).cpu().numpy()
+    x_ref = np.load(os.path.join(ROOT, "tests", "golden", "qp_sweep_instance0.npy"))
+    err0 = float(np.linalg.norm(X[:, 0] - x_ref) / np.linalg.norm(x_ref))
+    log(f"batched: {ms:.1f} ms for {N} instances, iterations mean {its.mean():.0f} max {its.max()}; "
+        f"instance 0 vs the FP64 optimum {err0:.2e}")
+    # one instance per launch (the plain path), on the first instances
+    k = wl["plain"]
+    plain = Plan(A, problem="qp", lam=P.lam, beta=beta, precision="fp32", max_batch=1)
+    plain.solve(b[:, :1], tol=wl["tol"], max_iter=wl["max_iter"])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for j in range(k):
+        plain.solve(b[:, j:j + 1], tol=wl["tol"], max_iter=wl["max_iter"])
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t) / k
+    value = N / (ms / 1e3)
+    out = {
+        "metric": "solves/s, QP_lambda sweep (batched DALM, FP32)", "value": round(value, 2), "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Gaussian compressive-sensing sweep)",
+        "config": {"workload": args.workload, "m": m, "n": n, "N": N, "problem": "QP_lambda", "lambda": P.lam,
+                   "beta": beta, "method": "dalm", "precision": "fp32", "tol": wl["tol"]},
+        "plan_ms": round(plan_ms, 1),
+        "iterations": {"mean": float(its.mean()), "max": int(its.max())},
+        "status_counts": np.bincount(r.status.cpu().numpy(), minlength=3).tolist(),
+        "rel_err_instance0_vs_fp64_optimum": err0,
+        "kkt_max": {"dual_inf": float(rep[:, 1].max()), "gap": float(rep[:, 3].max())},
+        "plain": {"solves_per_s": round(1.0 / plain_s, 3), "instances": k, "batched_over_plain": round(value * plain_s, 1)},
+    }
+    # roofline of the iteration launch: FP32 products, P (n x n) read once per launch
+    if timed_n > 0:
+        launch_s = timed_ms / 1e3 / timed_n
+        n_pad = -(-n // 64) * 64
+        cols = float(its.mean()) * N / float(its.max())    # average active instances per launch
+        flops = 2.0 * n * n * cols
+        bytes_ = 4.0 * n_pad * n_pad + cols * n * 28
+        t_mfma, t_hbm = flops / 157.3e12, bytes_ / (PEAK_HBM_GBS * 1e9)
+        if t_mfma >= t_hbm:
+            out["roofline"] = {"bound": "mfma", "achieved": round(flops / launch_s / 1e12, 2), "peak": 157.3,
+                               "unit": "TFLOP/s", "frac": round(flops / launch_s / 1e12 / 157.3, 4)}
+        else:
+            out["roofline"] = {"bound": "hbm", "achieved": round(bytes_ / launch_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                               "unit": "GB/s", "frac": round(bytes_ / launch_s / 1e9 / PEAK_HBM_GBS, 4)}
+        out["roofline"].update({"traffic": None, "avg_launch_us": round(1e6 * launch_s, 2),
+                                "kernel": "DALM iteration launch (FP32), HIP events",
+                                "avg_active_instances": round(cols, 1)})
+    if not args.no_cpu_baseline:
+        from oracle import dalm as oracle_dalm
+        K = 100
+        t = time.perf_counter()
+        oracle_dalm(P.A, P.b[:, :1], problem="qp", lam=P.lam, beta=beta, fixed_iters=K)
+        dt = time.perf_counter() - t
+        per_solve = dt / K * float(its.mean())
+        out["cpu_baseline"] = {"value": round(1.0 / per_solve, 4), "unit": "solves/s", "cores": _threads(),
+                               "kind": "oracle",
+                               "sample": f"{K} iterations of instance 0 ({dt:.1f} s, FP64 with a Cholesky "
+                                         f"y-step), extrapolated to the batch's mean iteration count"}
+    print(json.dumps(out), flush=True)
+
+
+def unrolled_main(args):
+    """Differentiable unrolled DALM: time of one forward (fixed iteration
+    count, checkpointed) and backward (gradients to b and B) over the batch;
+    the gradients against the oracle's reverse mode."""
+    import numpy as np
+    import torch
+
+    from paper_1007_3753_amd import Plan
+    from workloads import cab_problem
+
+    wl = UNROLLED_WORKLOADS[args.workload]
+    P = cab_problem(m=1200, classes=100, per_class=7, N=wl["N"], cfg=wl["cfg"])
+    N, K = wl["N"], wl["iters"]
+    dev = torch.device("cuda:0")
+    A = torch.as_tensor(P.A, device=dev)
+    b = torch.as_tensor(P.b, device=dev)
+    plan = Plan(A, structure="cab", precision="fp32", max_batch=N, record_tape=True, checkpoint_every=wl["every"])
+    r = np.random.default_rng([10073753, 77, 1])
+    gx_np, ge_np = r.standard_normal((P.n_dict, N)), r.standard_normal((P.m, N))
+    gx = torch.as_tensor(gx_np, dtype=torch.float32, device=dev)
+    ge = torch.as_tensor(ge_np, dtype=torch.float32, device=dev)
+
+    def step():
+        plan.solve(b, max_iter=-K, want_y=False)
+        return plan.backward(gx, ge)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        gb, gB = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / args.steps
+    # forward alone
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan.solve(b, max_iter=-K, want_y=False)
+    torch.cuda.synchronize()
+    fwd_ms = 1e3 * (time.perf_counter() - t)
+    n = P.n_dict + P.m
+    # forward K products, backward K recomputed + K reverse products (2 n^2 each per instance)
+    flops = 3.0 * K * 2.0 * n * n * N
+    out = {
+        "metric": "ms per forward + backward, unrolled DALM (gradients to b and B)", "value": round(ms, 3),
+        "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded cross-and-bouquet stand-in, 30 % corruption; random output adjoints)",
+        "config": {"workload": args.workload, "m": P.m, "n_dict": P.n_dict, "N": N, "iterations": K,
+                   "checkpoint_every": wl["every"]},
+        "forward_ms": round(fwd_ms, 3),
+        "roofline": {"bound": "mfma", "achieved": round(flops / (ms / 1e3) / 1e12, 3), "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": round(flops / (ms / 1e3) / 1e12 / 157.3, 4), "traffic": None,
+                     "kernel": "whole forward + backward (FP32 products; 3 products of P per iteration), wall clock"},
+    }
+    if not args.no_check or not args.no_cpu_baseline:
+        from oracle import unrolled_vjp
+        beta = np.abs(P.b.astype(np.float64)).sum(axis=0) / P.m
+        t = time.perf_counter()
+        gb_o, gB_o = unrolled_vjp(P.A, P.b, beta, K, gx_np, ge_np)
+        dt = time.perf_counter() - t
+        gbn, gBn = gb.cpu().numpy().astype(np.float64), gB.cpu().numpy().astype(np.float64)
+        out["grad_rel_err_vs_oracle"] = {
+            "b": float(np.linalg.norm(gbn - gb_o) / np.linalg.norm(gb_o)),
+            "B": float(np.linalg.norm(gBn - gB_o) / np.linalg.norm(gB_o))}
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = {"value": round(1e3 * dt, 1), "unit": "ms", "cores": _threads(), "kind": "oracle",
+                                   "sample": f"the whole batch ({N} instances), FP64 forward and reverse mode"}
+    log(f"forward + backward {ms:.1f} ms (forward {fwd_ms:.1f} ms); {out.get('grad_rel_err_vs_oracle')}")
     print(json.dumps(out), flush=True)
 
 
