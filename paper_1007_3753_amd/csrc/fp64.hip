@@ -1,8 +1,7 @@
 // FP64 kernels: the one-time factorisation of a plan (Gram matrix, blocked
 // Cholesky, triangular inverse, operator assembly, power iteration for the
-// FISTA step) and the FP64 optimality report.  gfx950 runs FP64 FMA on the
-// vector ALUs at the same peak as the FP64 matrix cores, so these kernels are
-// plain LDS-tiled VALU code.
+// FISTA step) and the FP64 optimality report.  The GEMM runs on the FP64
+// matrix cores; the rest is LDS-tiled vector code.
 #include "internal.h"
 
 #include <cmath>
@@ -10,24 +9,31 @@
 namespace l1 {
 
 // ---------------------------------------------------------------------------
-// GEMM: C = alpha op(A) op(B) + beta C (column-major).  64x64 tile, 256
-// threads, 4x4 register block per thread, K staged through LDS 16 at a time.
+// GEMM: C = alpha op(A) op(B) + beta C (column-major), on the FP64 matrix
+// cores.  64x64 tile per workgroup, K staged through LDS 16 at a time; wave w
+// computes the 32x32 quarter (w / 2, w % 2) as 2x2 blocks of
+// v_mfma_f64_16x16x4f64.  Operand lane layout: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] of a 16x4 / 4x16 step; accumulator register v of lane
+// l holds D[l / 16 + 4 v][l % 16].
+typedef double v4d64 __attribute__((ext_vector_type(4)));
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm64_kernel(int M, int N, int K, double alpha,
                                                      const double* __restrict__ A, int lda,
                                                      const double* __restrict__ B, int ldb,
                                                      double beta, double* __restrict__ C,
                                                      int ldc) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  __shared__ double As[16][68];   // As[k][i]
+  __shared__ double Bs[16][68];   // Bs[k][j]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fi = lane & 15, fk = lane >> 4;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-  double acc[4][4];
+  v4d64 acc[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d64{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -51,32 +57,31 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int M, int N, int K, double
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kk][tx + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][ty + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kr = 4 * ks + fk;
+      const double a0 = As[kr][wr + fi], a1 = As[kr][wr + 16 + fi];
+      const double b0 = Bs[kr][wc + fi], b1 = Bs[kr][wc + 16 + fi];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int gi = i0 + tx + 16 * r;
-    if (gi >= M) continue;
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int gj = j0 + ty + 16 * c;
-      if (gj >= N) continue;
-      double* p = C + gi + (long)gj * ldc;
-      const double v = alpha * acc[r][c];
-      *p = (beta == 0.0) ? v : v + beta * (*p);
-    }
-  }
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wr + 16 * bi + fk + 4 * v;
+        const int gj = j0 + wc + 16 * bj + fi;
+        if (gi < M && gj < N) {
+          double* p = C + gi + (long)gj * ldc;
+          const double r = alpha * acc[bi][bj][v];
+          *p = (beta == 0.0) ? r : r + beta * (*p);
+        }
+      }
 }
 
 void gemm64(hipStream_t s, char ta, char tb, int M, int N, int K, double alpha,
