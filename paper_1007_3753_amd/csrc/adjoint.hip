@@ -285,18 +285,37 @@ void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* 
   full_matrix64_kernel<<<blocks_for((long)m * n), 256, 0, s>>>(m, nd, n, p->A, A64);
   L1_HIP(hipGetLastError());
   double* G = bf.get<double>((size_t)m * m);
-  double* X = bf.get<double>((size_t)m * m);
-  double* M = bf.get<double>((size_t)m * m);
-  double* dinv = bf.get<double>((size_t)((m + 63) / 64) * 64 * 64);
-  double* work = bf.get<double>((size_t)128 * m);
-  int* info = bf.get<int>(1);
-  gemm64(s, 'N', 'T', m, m, n, 1.0, A64, m, A64, m, 0.0, G, m);
-  if (p->shift != 0.0) add_diag64(s, m, G, m, p->shift);
-  potrf64(s, m, G, m, dinv, info, work);
-  lower_inverse64(s, m, G, m, dinv, X, m, work);
-  gemm64(s, 'T', 'N', m, m, m, 1.0, X, m, X, m, 0.0, M, m);   // M = L^{-T} L^{-1}
-  double* Y = bf.get<double>((size_t)m * n);
-  gemm64(s, 'N', 'N', m, n, m, 1.0, M, m, A64, m, 0.0, Y, m);  // Y = M A
+  if (!p->adj_M) {
+    // M = (A A^T + shift I)^{-1} and Y = M A depend only on the dictionary:
+    // formed once per plan
+    double* Mk = nullptr;
+    double* Yk = nullptr;
+    // owned by the plan from here on (freed with it), valid once formed
+    if (hipMalloc((void**)&Mk, sizeof(double) * (size_t)m * m) == hipSuccess) p->owned.push_back(Mk);
+    else Mk = nullptr;
+    if (Mk && hipMalloc((void**)&Yk, sizeof(double) * (size_t)m * n) == hipSuccess) p->owned.push_back(Yk);
+    else Yk = nullptr;
+    if (!Mk || !Yk) {
+      (void)hipGetLastError();
+      set_error("out of device memory in l1_alm_backward");
+      throw Fail{L1_ENOMEM};
+    }
+    double* X = bf.get<double>((size_t)m * m);
+    double* dinv = bf.get<double>((size_t)((m + 63) / 64) * 64 * 64);
+    double* work = bf.get<double>((size_t)128 * m);
+    int* info = bf.get<int>(1);
+    gemm64(s, 'N', 'T', m, m, n, 1.0, A64, m, A64, m, 0.0, G, m);
+    if (p->shift != 0.0) add_diag64(s, m, G, m, p->shift);
+    potrf64(s, m, G, m, dinv, info, work);
+    lower_inverse64(s, m, G, m, dinv, X, m, work);
+    gemm64(s, 'T', 'N', m, m, m, 1.0, X, m, X, m, 0.0, Mk, m);   // M = L^{-T} L^{-1}
+    gemm64(s, 'N', 'N', m, n, m, 1.0, Mk, m, A64, m, 0.0, Yk, m);  // Y = M A
+    L1_HIP(hipStreamSynchronize(s));
+    p->adj_M = Mk;
+    p->adj_Y = Yk;
+  }
+  const double* M = p->adj_M;
+  const double* Y = p->adj_Y;
   double* bt = bf.get<double>((size_t)m * N);
   scale_cols64_kernel<<<blocks_for((long)m * N), 256, 0, s>>>(m, N, p->tape_b, p->m_pad, ibeta,
                                                               bt, m);

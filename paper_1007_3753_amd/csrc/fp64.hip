@@ -10,12 +10,14 @@ namespace l1 {
 
 // ---------------------------------------------------------------------------
 // GEMM: C = alpha op(A) op(B) + beta C (column-major), on the FP64 matrix
-// cores.  64x64 tile per workgroup, K staged through LDS 16 at a time; wave w
+// cores.  64x64 tile per workgroup, K staged through LDS 32 at a time (the
+// next slice's global loads in flight during the current one's MFMAs); wave w
 // computes the 32x32 quarter (w / 2, w % 2) as 2x2 blocks of
 // v_mfma_f64_16x16x4f64.  Operand lane layout: lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16] of a 16x4 / 4x16 step; accumulator register v of lane
 // l holds D[l / 16 + 4 v][l % 16].
 typedef double v4d64 __attribute__((ext_vector_type(4)));
+constexpr int G64_KS = 32;   // K slice staged through LDS
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm64_kernel(int M, int N, int K, double alpha,
@@ -23,8 +25,8 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int M, int N, int K, double
                                                      const double* __restrict__ B, int ldb,
                                                      double beta, double* __restrict__ C,
                                                      int ldc) {
-  __shared__ double As[16][68];   // As[k][i]
-  __shared__ double Bs[16][68];   // Bs[k][j]
+  __shared__ double As[G64_KS][68];   // As[k][i]
+  __shared__ double Bs[G64_KS][68];   // Bs[k][j]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int fi = lane & 15, fk = lane >> 4;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -34,30 +36,42 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int M, int N, int K, double
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d64{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  // the next slice's elements of this thread, loaded while the current one
+  // is multiplied (8 of A and 8 of B; the index along the contiguous
+  // dimension of each operand runs over consecutive threads)
+  double pa[8], pb[8];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < 8; ++t) {
       const int e = tid + t * 256;
       int ii, kk;
-      if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+      if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e & 31; ii = e >> 5; }
       const int gi = i0 + ii, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < M && gk < K) v = TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
-      As[kk][ii] = v;
+      pa[t] = (gi < M && gk < K) ? (TA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda]) : 0.0;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < 8; ++t) {
       const int e = tid + t * 256;
       int jj, kk;
-      if (!TB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
+      if (!TB) { kk = e & 31; jj = e >> 5; } else { jj = e & 63; kk = e >> 6; }
       const int gj = j0 + jj, gk = k0 + kk;
-      double v = 0.0;
-      if (gj < N && gk < K) v = TB ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb];
-      Bs[kk][jj] = v;
+      pb[t] = (gj < N && gk < K) ? (TB ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb]) : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += G64_KS) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + t * 256;
+      if (!TA) As[e >> 6][e & 63] = pa[t];
+      else As[e & 31][e >> 5] = pa[t];
+      if (!TB) Bs[e & 31][e >> 5] = pb[t];
+      else Bs[e >> 6][e & 63] = pb[t];
     }
     __syncthreads();
+    if (k0 + G64_KS < K) load(k0 + G64_KS);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < G64_KS / 4; ++ks) {
       const int kr = 4 * ks + fk;
       const double a0 = As[kr][wr + fi], a1 = As[kr][wr + 16 + fi];
       const double b0 = Bs[kr][wc + fi], b1 = Bs[kr][wc + 16 + fi];

@@ -58,6 +58,11 @@ struct Plan {
   std::vector<void*> tape;
   int tape_N = 0, tape_K = 0, tape_every = 0;   // tape_N = 0: no complete tape
   float* tape_b = nullptr;    // b of the recorded solve (m_pad x N)
+  // the backward's FP64 (A A^T + shift I)^{-1} (m x m) and its product with
+  // the full matrix A (m x n): depend only on the dictionary, formed by the
+  // first l1_alm_backward and kept (owned)
+  double* adj_M = nullptr;
+  double* adj_Y = nullptr;
   float* tape_pen = nullptr;  // its beta (N) and 1/beta (N)
 };
 
