@@ -51,6 +51,35 @@ struct Bufs {
   }
 };
 
+// Workspaces of the backward that the plan keeps: the k-th request of a call
+// gets the k-th kept buffer when it is large enough (the requests come in the
+// same order in every call), else a new one replaces it.  The previous
+// backward ended with a stream synchronisation, so no kernel still uses a
+// buffer that is replaced.
+struct Arena {
+  Plan* p;
+  size_t i = 0;
+  template <class T>
+  T* get(size_t n) {
+    const size_t bytes = sizeof(T) * std::max<size_t>(n, 1);
+    auto& v = p->adj_ws;
+    if (i < v.size() && v[i].first >= bytes) return reinterpret_cast<T*>(v[i++].second);
+    if (i < v.size()) {
+      (void)hipFree(v[i].second);
+      v[i] = {0, nullptr};
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("out of device memory in l1_alm_backward");
+      throw Fail{L1_ENOMEM};
+    }
+    if (i < v.size()) v[i] = {bytes, q};
+    else v.push_back({bytes, q});
+    return reinterpret_cast<T*>(v[i++].second);
+  }
+};
+
 // wbar = [gx; ge] (the adjoints of the outputs), vt = beta wbar (vbar_K = 0)
 __global__ void adj_init_kernel(int nd, int m, int split, int n, int lds, int N, const float* gx,
                                 const float* ge, const float* beta, float* Wb, float* Vt) {
@@ -156,7 +185,8 @@ void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* 
   L1_HIP(hipEventRecord(ev, us));
   L1_HIP(hipStreamWaitEvent(s, ev, 0));
 
-  Bufs bf;
+  Arena bf{p};
+  Bufs once;   // buffers of the one-time factorisation
   const size_t st = (size_t)lds * N;
   float* Wb = bf.get<float>(st);
   float* Vt = bf.get<float>(st);
@@ -300,10 +330,10 @@ void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* 
       set_error("out of device memory in l1_alm_backward");
       throw Fail{L1_ENOMEM};
     }
-    double* X = bf.get<double>((size_t)m * m);
-    double* dinv = bf.get<double>((size_t)((m + 63) / 64) * 64 * 64);
-    double* work = bf.get<double>((size_t)128 * m);
-    int* info = bf.get<int>(1);
+    double* X = once.get<double>((size_t)m * m);
+    double* dinv = once.get<double>((size_t)((m + 63) / 64) * 64 * 64);
+    double* work = once.get<double>((size_t)128 * m);
+    int* info = once.get<int>(1);
     gemm64(s, 'N', 'T', m, m, n, 1.0, A64, m, A64, m, 0.0, G, m);
     if (p->shift != 0.0) add_diag64(s, m, G, m, p->shift);
     potrf64(s, m, G, m, dinv, info, work);

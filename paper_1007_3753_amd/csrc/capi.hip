@@ -284,6 +284,8 @@ void destroy_plan(Plan* p) {
   (void)hipSetDevice(p->dev);
   (void)hipDeviceSynchronize();
   for (void* q : p->owned) (void)hipFree(q);
+  for (auto& w : p->adj_ws)
+    if (w.second) (void)hipFree(w.second);
   for (void* q : p->tape) (void)hipFree(q);
   if (p->h_total) (void)hipHostFree(p->h_total);
   if (cur >= 0) (void)hipSetDevice(cur);

@@ -63,6 +63,9 @@ struct Plan {
   // first l1_alm_backward and kept (owned)
   double* adj_M = nullptr;
   double* adj_Y = nullptr;
+  // the backward's workspaces (bytes, pointer), taken in the order the
+  // backward asks for them and kept for the next call (freed with the plan)
+  std::vector<std::pair<size_t, void*>> adj_ws;
   float* tape_pen = nullptr;  // its beta (N) and 1/beta (N)
 };
 
