@@ -605,6 +605,15 @@ def qp_main(args):
     beta = float(np.mean(np.abs(P.b.astype(np.float64)).sum(0) / m))   # one beta: it enters the factor
     plan = Plan(A, problem="qp", lam=P.lam, beta=beta, precision="fp32", max_batch=N, time_kernels=True)
     plan_ms = plan.last_stats()["plan_ms"]
+    from paper_1007_3753_amd import tuning
+    if args.tune:
+        t0 = time.perf_counter()
+        table = tuning.tune(plan, path=args.tune_out or tuning.CACHE)
+        ks_info = {"source": "tuned in this run", "table": table, "tune_s": round(time.perf_counter() - t0, 2)}
+    else:
+        table = tuning.apply(plan)
+        ks_info = {"source": "cache" if table is not None else "heuristic", "table": table}
+    log(f"split-K table: {ks_info}")
     for _ in range(args.warmup):
         plan.solve(b, tol=wl["tol"], max_iter=wl["max_iter"])
     torch.cuda.synchronize()
@@ -643,6 +652,7 @@ def qp_main(args):
         "config": {"workload": args.workload, "m": m, "n": n, "N": N, "problem": "QP_lambda", "lambda": P.lam,
                    "beta": beta, "method": "dalm", "precision": "fp32", "tol": wl["tol"]},
         "plan_ms": round(plan_ms, 1),
+        "ksplit": ks_info,
         "iterations": {"mean": float(its.mean()), "max": int(its.max())},
         "status_counts": np.bincount(r.status.cpu().numpy(), minlength=3).tolist(),
         "rel_err_instance0_vs_fp64_optimum": err0,

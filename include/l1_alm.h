@@ -202,9 +202,10 @@ int l1_alm_set_ksplit(l1_alm_plan_t plan, const int* ks_by_tiles, int n);
  * max_batch / 64) it times fixed-count solves of t * 64 synthetic right-hand
  * sides (`iters` iterations each, median of 3, HIP events on `stream`) for
  * every split 1..L1_KSPLIT_MAX, keeps the fastest in the plan and writes the
- * table (n entries, t = 1..n; entry 1 stays 0: with one active column tile
- * the tail kernel takes over and uses the heuristic's split) to ks_out (host
- * memory).  The timings run in the plan's first arithmetic (BF16 for
+ * table (n entries, t = 1..n) to ks_out (host memory).  Entry 1 (one active
+ * column tile) stays 0 where the tail kernel can take over the last
+ * instances (it uses the heuristic's split); for operators too large for the
+ * tail kernel (more than 2048 padded columns) t = 1 is tuned as well.  The timings run in the plan's first arithmetic (BF16 for
  * L1_BF16_REFINE).  Allocates and frees its own device buffers; the solve
  * workspace of the plan is overwritten.  Errors: L1_EINVAL for a non-DALM or
  * (P1,2) plan, iters outside [16, 4096] or a bad n.                        */

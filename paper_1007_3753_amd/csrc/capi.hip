@@ -10,6 +10,7 @@
 #include "internal.h"
 #include "plan.h"
 #include "readout.h"
+#include "tail.h"
 #include "steps.h"
 
 namespace l1 {
@@ -495,9 +496,12 @@ int l1_alm_tune_ksplit(l1_alm_plan_t plan, int iters, int* ks_out, int n, void* 
     L1_HIP(hipMemcpyAsync(b, hb.data(), sizeof(float) * hb.size(), hipMemcpyHostToDevice, s));
     L1_HIP(hipEventCreate(&e0));
     L1_HIP(hipEventCreate(&e1));
-    // one active column tile stays with the heuristic: the tail kernel
-    // takes over there and runs the parts the heuristic gives it
-    for (int t = 2; t <= tmax; ++t) {
+    // one active column tile stays with the heuristic when the tail kernel
+    // can take over there (it runs the parts the heuristic gives it); when
+    // its workgroups could not hold the operator rows it never runs, and the
+    // one-tile shape is tuned too
+    const bool tail_possible = p->n_pad / TAIL_ROWS <= 16 * TAIL_TG;
+    for (int t = tail_possible ? 2 : 1; t <= tmax; ++t) {
       const int N = t * TILE;
       SolveArgs a{b, m, N, nullptr, 0.0f, -iters, nullptr, nullptr, x, nd, nullptr, 0,
                   nullptr, 0, it, st, s};
