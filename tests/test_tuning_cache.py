@@ -41,4 +41,5 @@ def test_committed_cache_is_well_formed():
         arch, structure, problem, m, n, batch, prec = key.split("|")
         assert arch.startswith("gfx") and m.startswith("m") and n.startswith("n") and batch.startswith("batch")
         t = entry["ksplit"]
-        assert len(t) == 8 and t[0] == 0 and all(0 <= v <= 4 for v in t)
+        # entry 1 is tuned only for operators too large for the tail kernel
+        assert len(t) == 8 and all(0 <= v <= 4 for v in t)
