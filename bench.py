@@ -21,9 +21,62 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks (dense): HBM3E 8 TB/s; MFMA BF16 2.5 PFLOP/s, FP32 157.3 TFLOP/s
+# MI355X published peaks (dense): HBM3E 8 TB/s; MFMA BF16 2.5 PFLOP/s, FP32 157.3 TFLOP/s.
+# A split-BF16 product issues three BF16 MFMAs per algorithmic multiply-add
+# (hi*hi + hi*lo + lo*hi), so its algorithmic flops run at a third of the peak.
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "split": 2500.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "split": 2500.0 / 3.0}
+ELEM_BYTES = {"fp32": 4, "bf16": 2, "split": 4}
+
+
+def dalm_work_model(m, n_dict, structure):
+    """Algorithmic work of one DALM iteration of one instance (the method's
+    own: two products with the dictionary and the two triangular solves with
+    the Cholesky factor of the y-step, Algorithm 2), and the matrix bytes one
+    batched iteration reads once:
+        flops   F = 4 m n_B + 2 m^2
+        matrix  2 m n_B s (the dictionary twice, s bytes per element in the
+                product's arithmetic) + 4 m^2 (the FP32 factor, both solves)
+        state   4 (4 n + 5 m + 2 n_B) bytes per instance (FP32 state, fused
+                updates; n = n_B + m for the cross-and-bouquet form)."""
+    n = n_dict + (m if structure == "cab" else 0)
+    return {"flops": 4.0 * m * n_dict + 2.0 * m * m,
+            "matrix": lambda s: 2.0 * m * n_dict * s + 4.0 * m * m,
+            "state": 4.0 * (4 * n + 5 * m + 2 * n_dict)}
+
+
+def dalm_roofline(m, n_dict, structure, agg, kern_s, launches):
+    """Roofline of the DALM iteration over a timed run: instance-iterations
+    by arithmetic (agg cols_*), iterations of the slowest instance (one
+    batched iteration each: the matrices are read once per iteration), and
+    the kernel time from HIP events.  The bound is the larger of the MFMA
+    time (each arithmetic at its peak) and the HBM time."""
+    wm = dalm_work_model(m, n_dict, structure)
+    cols = {"fp32": agg["cols_fp32"], "bf16": agg["cols_bf16"], "split": agg["cols_split"]}
+    tot_cols = max(sum(cols.values()), 1.0)
+    flops = {k: wm["flops"] * c for k, c in cols.items()}
+    s_avg = sum(ELEM_BYTES[k] * c for k, c in cols.items()) / tot_cols
+    bytes_total = agg["iterations"] * wm["matrix"](s_avg) + wm["state"] * tot_cols
+    tot_flops = sum(flops.values())
+    t_mfma = sum(flops[k] / (PEAK_TFLOPS[k] * 1e12) for k in flops)
+    t_hbm = bytes_total / (PEAK_HBM_GBS * 1e9)
+    nl = max(launches, 1.0)
+    if t_mfma >= t_hbm:
+        eff_peak = tot_flops / t_mfma / 1e12
+        achieved = tot_flops / kern_s / 1e12 if kern_s > 0 else 0.0
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(eff_peak, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / eff_peak, 4)}
+    else:
+        achieved = bytes_total / kern_s / 1e9 if kern_s > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    roof.update({"avg_launch_us": round(1e6 * kern_s / nl, 3), "launches_timed": int(launches),
+                 "algorithmic_flops_per_launch": round(tot_flops / nl),
+                 "algorithmic_bytes_per_launch": round(bytes_total / nl),
+                 "flops_per_instance_iteration": wm["flops"],
+                 "state_bytes_per_instance": wm["state"],
+                 "t_mfma_s": t_mfma, "t_hbm_s": t_hbm})
+    return roof, tot_flops, bytes_total
 
 WORKLOADS = {
     # B 1200 x 700 (100 classes x 7), A = [B, I]; 512 test vectors, 30 % corrupted
@@ -81,7 +134,7 @@ def parse():
                     help="instances whose x is compared with the exact LP optimum")
     ap.add_argument("--plain-instances", type=int, default=8,
                     help="instances solved one per launch with FP32 for the plain-path figure")
-    ap.add_argument("--cpu-instances", type=int, default=4,
+    ap.add_argument("--cpu-instances", type=int, default=8,
                     help="instances the FP64 CPU oracle solves for the cpu_baseline figure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
@@ -189,54 +242,23 @@ def main():
     status = r.status.cpu().numpy()
     rep = rep.cpu().numpy()
     log(f"{args.steps} steps: {ms_per_step:.2f} ms/step -> {value:.1f} solves/s; iterations "
-        f"mean {iters.mean():.0f} max {iters.max()}; status counts {np.bincount(status, minlength=3).tolist()}")
+        f"mean {iters.mean():.0f} max {iters.max()}; status counts {np.bincount(status, minlength=4).tolist()}")
 
     # ---- roofline of the iteration kernel (gemm_kernel<EPI_DALM>) -----------
-    n_pad = (n_full + 63) // 64 * 64
-    cols = {"fp32": agg["cols_fp32"], "bf16": agg["cols_bf16"], "split": agg["cols_split"]}
-    flops = {k: 2.0 * n_full * n_full * c for k, c in cols.items()}
     kern_s = agg["timed_ms"] / 1e3
     nl = max(agg["timed_launches"], 1.0)
-    # algorithmic bytes of one launch: the operator read once, in the element
-    # size of the arithmetic (weighted by the instances each arithmetic
-    # served), plus per instance the operand u read in that arithmetic
-    # (FP32 4 B, BF16 2 B, split 4 B), v, w, c read, v, w written and the next
-    # u written in the arithmetic of its next product (FP32, or the BF16
-    # hi / lo split: 4 B either way)
-    esize = {"fp32": 4, "bf16": 2, "split": 4}
-    tot_cols = max(sum(cols.values()), 1.0)
-    # the operator is read once by every launch that had work (one per
-    # iteration of the slowest instance)
-    op_bytes = agg["iterations"] * n_full * n_full * sum(esize[k] * cols[k] for k in cols) / tot_cols
-    bytes_total = op_bytes + n_full * sum(cols[k] * (esize[k] + 24) for k in cols)
-    t_mfma = sum(flops[k] / (PEAK_TFLOPS[k] * 1e12) for k in flops)
-    t_hbm = bytes_total / (PEAK_HBM_GBS * 1e9)
-    tot_flops = sum(flops.values())
+    roof, tot_flops, bytes_total = dalm_roofline(m, nd, "cab", agg, kern_s, nl)
     trec = traffic_record(kernel_source_hash())
-    traffic = None if trec is None else trec.get("hbm_bytes_per_launch_at_workload", {}).get(args.workload)
-    if t_mfma >= t_hbm:
-        eff_peak = tot_flops / t_mfma / 1e12 if t_mfma > 0 else 0.0
-        achieved = tot_flops / kern_s / 1e12 if kern_s > 0 else 0.0
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(eff_peak, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / eff_peak, 4) if eff_peak else None,
-                "traffic": traffic}
-    else:
-        achieved = bytes_total / kern_s / 1e9 if kern_s > 0 else 0.0
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+    roof["traffic"] = None if trec is None else trec.get("hbm_bytes_per_launch_at_workload", {}).get(args.workload)
     roof.update({
         "kernel": "DALM iteration: gemm_kernel<EPI_DALM> (+ its split-K gemm_kernel<EPI_PARTIAL> "
                   "launch when few column tiles are active, + 1/16 of a compaction), or one "
-                  "iteration of dalm_tail_kernel once at most 6 instances are left",
-        "avg_launch_us": round(1e6 * kern_s / nl, 3),
-        "launches_timed": int(agg["timed_launches"]),
-        "algorithmic_flops_per_launch": round(tot_flops / nl),
-        "algorithmic_bytes_per_launch": round(bytes_total / nl),
-        "mfma_frac_of_bf16_peak": round(tot_flops / kern_s / 2.5e15, 4) if kern_s > 0 else None,
+                  "iteration of dalm_tail_kernel once few instances are left",
         "kernel_share_of_step": round(agg["timed_ms"] / (ms_per_step * args.steps), 3),
     })
     log(f"iteration kernel: {nl:.0f} launches, avg {1e6 * kern_s / nl:.2f} us; "
-        f"{tot_flops / kern_s / 1e12:.1f} algorithmic TFLOP/s, {bytes_total / kern_s / 1e9:.0f} GB/s")
+        f"{tot_flops / kern_s / 1e12:.1f} algorithmic TFLOP/s, {bytes_total / kern_s / 1e9:.0f} GB/s "
+        f"({roof['bound']}-bound, {100 * roof['frac']:.1f} % of the roofline)")
 
     out = {
         "metric": "solves/sec at rel. err <=1e-4 vs FP64 oracle (batched DALM, cross-and-bouquet)",
@@ -252,7 +274,7 @@ def main():
         "plan_ms": round(plan_ms, 2),
         "ksplit": ks_info,
         "iterations": {"mean": float(iters.mean()), "max": int(iters.max())},
-        "status_counts": np.bincount(status, minlength=3).tolist(),
+        "status_counts": np.bincount(status, minlength=4).tolist(),
         "kkt_max": {"primal": float(rep[:, 0].max()), "dual_inf": float(rep[:, 1].max()),
                     "gap": float(rep[:, 3].max())},
         "roofline": roof,
@@ -266,7 +288,19 @@ def main():
     out["rel_err_vs_planted"] = {"instances": int(N), "max": float(err_pl.max()),
                                  "p99": float(np.quantile(err_pl, 0.99)),
                                  "median": float(np.median(err_pl))}
-    log(f"rel. err of x vs planted solution, all {N} instances: max {err_pl.max():.2e}")
+    out["rel_err_vs_planted"]["within_1e-4"] = int((err_pl <= 1e-4).sum())
+    out["rel_err_vs_planted"]["within_1e-3"] = int((err_pl <= 1e-3).sum())
+    log(f"rel. err of x vs planted solution, all {N} instances: max {err_pl.max():.2e}; "
+        f"{int((err_pl <= 1e-4).sum())} within 1e-4, {int((err_pl <= 1e-3).sum())} within 1e-3")
+    gpath = os.path.join(ROOT, "tests", "golden", "c4_reference.npz")
+    if args.workload == "cab-4800x2100-n2048" and os.path.exists(gpath):
+        # the exact LP optima (oracle, certified) of the golden sample
+        g = np.load(gpath)
+        ge = [float(np.linalg.norm(X[:, j] - g["w"][:nd, k]) / np.linalg.norm(g["w"][:nd, k]))
+              for k, j in enumerate(g["idx"])]
+        out["rel_err_vs_lp"] = {"instances": [int(j) for j in g["idx"]], "max": max(ge), "all": ge,
+                                "corruption": [round(float(f), 3) for f in g["frac"]]}
+        log(f"rel. err of x vs the LP optima of the golden sample: max {max(ge):.2e}")
     # the recognition criterion of the face experiments (Sec. VI-B) on the
     # solved batch: every test vector is drawn from one subject's columns
     from paper_1007_3753_amd import classify
@@ -290,7 +324,7 @@ def main():
     rrate = float((rlabel.cpu().numpy() == P.labels).mean())
     out["recognition"]["residual_rule"] = {"rate": rrate, "ms": round(res_ms, 3)}
     log(f"recognition (residual rule): {100 * rrate:.1f} % of {N} in {res_ms:.2f} ms")
-    if not args.no_check and args.check_instances > 0:
+    if not args.no_check and args.check_instances > 0 and m <= 2000:
         from oracle import p1_lp, full_matrix
         Af = full_matrix(P.A, "cab")
         idx = np.unique(np.linspace(0, N - 1, args.check_instances).astype(int))
@@ -322,23 +356,48 @@ def main():
 
     # ---- CPU baseline: the FP64 oracle on this host's cores ------------------
     if not args.no_cpu_baseline and args.cpu_instances > 0:
-        from oracle import dalm as oracle_dalm
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        except Exception:
-            threads = os.cpu_count()
+        from oracle import dalm as oracle_dalm, kkt_report, full_matrix
+        threads = _threads()
         k = min(args.cpu_instances, N)
-        t = time.perf_counter()
-        o = oracle_dalm(P.A, P.b[:, :k], structure="cab", tol=args.tol, max_iter=args.max_iter)
-        dt = time.perf_counter() - t
-        out["cpu_baseline"] = {
-            "value": round(k / dt, 5), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {k} of the {N} instances, FP64 NumPy/SciPy Algorithm 2 with a "
-                      f"Cholesky y-step, same tol ({args.tol:g}); {dt:.1f} s, iterations "
-                      f"{o.iters.tolist()}"}
-        log(f"CPU oracle: {k} instances in {dt:.1f} s on {threads} threads")
+        if m <= 2000:
+            # like for like: the first k instances solved to the same tolerance
+            t = time.perf_counter()
+            o = oracle_dalm(P.A, P.b[:, :k], structure="cab", tol=args.tol, max_iter=args.max_iter)
+            dt = time.perf_counter() - t
+            out["cpu_baseline"] = {
+                "value": round(k / dt, 5), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+                "sample": f"first {k} of the {N} instances, FP64 NumPy/SciPy Algorithm 2 with a "
+                          f"Cholesky y-step, same tol ({args.tol:g}); {dt:.1f} s, iterations "
+                          f"{o.iters.tolist()}; the rate extrapolates to the batch"}
+            log(f"CPU oracle: {k} instances in {dt:.1f} s on {threads} threads")
+            # ground truth (not timed for ranking): instance 0 to tol 1e-12
+            # with its FP64 certificate, and the GPU result against it
+            t = time.perf_counter()
+            g = oracle_dalm(P.A, P.b[:, :1], structure="cab", tol=1e-12, max_iter=400000)
+            gdt = time.perf_counter() - t
+            rep0 = kkt_report(full_matrix(P.A, "cab"), P.b[:, 0], g.w[:, 0], g.y[:, 0])
+            xg = g.w[:nd, 0]
+            out["cpu_ground_truth"] = {
+                "instance": 0, "tol": 1e-12, "iterations": int(g.iters[0]), "s": round(gdt, 2),
+                "kkt": rep0, "gpu_rel_err": float(np.linalg.norm(X[:, 0] - xg) / np.linalg.norm(xg))}
+            log(f"CPU ground truth (instance 0, tol 1e-12): {int(g.iters[0])} iterations, {gdt:.1f} s, "
+                f"KKT {rep0}; GPU rel. err {out['cpu_ground_truth']['gpu_rel_err']:.2e}")
+        else:
+            # a solve of this size takes minutes on the host: 100 iterations of
+            # instance 0, extrapolated to the batch's mean iteration count
+            K = 100
+            t = time.perf_counter()
+            oracle_dalm(P.A, P.b[:, :1], structure="cab", fixed_iters=K)
+            dt = time.perf_counter() - t
+            per_solve = dt / K * float(iters.mean())
+            out["cpu_baseline"] = {
+                "value": round(1.0 / per_solve, 6), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+                "sample": f"{K} iterations of instance 0 ({dt:.1f} s, FP64 Algorithm 2 with a Cholesky "
+                          f"y-step), extrapolated to the batch's mean iteration count "
+                          f"({float(iters.mean()):.0f})"}
+            log(f"CPU oracle: {K} iterations in {dt:.1f} s -> {per_solve:.0f} s per solve (extrapolated)")
 
+    plan.close()
     if args.copy_calibration:
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
@@ -424,7 +483,7 @@ def e1_main(args):
         "curve": {"columns": ["iterations", "ms", "mean_rel_err", "max_rel_err"], "points": curve},
         "converged": {"tol": 1e-6, "ms": round(conv_ms, 3), "iterations_max": int(rc.iters.max()),
                       "mean_rel_err": float(errc.mean()), "max_rel_err": float(errc.max()),
-                      "status_counts": np.bincount(rc.status.cpu().numpy(), minlength=3).tolist()},
+                      "status_counts": np.bincount(rc.status.cpu().numpy(), minlength=4).tolist()},
     }
     n = wl["n"]
     if args.method == "dalm" and agg is not None and agg["timed_launches"] > 0:
@@ -520,7 +579,7 @@ def align_main(args):
         its = it.cpu().numpy()
         per_tol[tol] = dict(ms=ms, wall_ms=1e3 * wall, iters_mean=float(its.mean()), iters_max=int(its.max()),
                             iters_total=int(its.sum()), err_mean=float(err.mean()), err_max=float(err.max()),
-                            status=np.bincount(st.cpu().numpy(), minlength=3).tolist())
+                            status=np.bincount(st.cpu().numpy(), minlength=4).tolist())
         log(f"tol {tol:g}: {ms:.3f} ms ({N / ms * 1e3:.0f} solves/s), iterations mean "
             f"{its.mean():.2f}, rel. err of w vs planted: mean {err.mean():.2e}")
     main_tol = wl["tol"]
@@ -569,6 +628,7 @@ def align_main(args):
             "value": round(N / dt, 2), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"all {N} instances, FP64 NumPy PALM, same tol; {dt:.1f} s, "
                       f"iterations mean {o.iters.mean():.2f}"}
+    plan.close()
     if args.copy_calibration:
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
@@ -654,7 +714,7 @@ def qp_main(args):
         "plan_ms": round(plan_ms, 1),
         "ksplit": ks_info,
         "iterations": {"mean": float(its.mean()), "max": int(its.max())},
-        "status_counts": np.bincount(r.status.cpu().numpy(), minlength=3).tolist(),
+        "status_counts": np.bincount(r.status.cpu().numpy(), minlength=4).tolist(),
         "rel_err_instance0_vs_fp64_optimum": err0,
         "kkt_max": {"dual_inf": float(rep[:, 1].max()), "gap": float(rep[:, 3].max())},
         "plain": {"solves_per_s": round(1.0 / plain_s, 3), "instances": k, "batched_over_plain": round(value * plain_s, 1)},
@@ -762,5 +822,15 @@ def unrolled_main(args):
     print(json.dumps(out), flush=True)
 
 
+def run():
+    """main() with a deterministic teardown: every plan is destroyed and the
+    device drained before the interpreter starts to shut down."""
+    try:
+        main()
+    finally:
+        if "paper_1007_3753_amd._lib" in sys.modules:
+            sys.modules["paper_1007_3753_amd._lib"].close_all()
+
+
 if __name__ == "__main__":
-    main()
+    run()

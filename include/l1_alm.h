@@ -48,6 +48,15 @@ extern "C" {
 #define L1_CONVERGED   0
 #define L1_MAXITER     1
 #define L1_NONFINITE   2
+/* L1_DIVERGED: the iterate left every bounded region the optimum can lie
+ * in: ||w_k||_2 > div_factor * sqrt(m) * ||b||_2 (desc.div_factor, default
+ * 1e6).  For (P1) on a cross-and-bouquet matrix every optimum satisfies
+ * ||w*||_2 <= ||w*||_1 <= ||b||_1 <= sqrt(m) ||b||_2 (w = [0; b] is
+ * feasible), so an iterate that far out is not converging.  The test runs
+ * with the stopping test (never in fixed-count solves); the exact DALM
+ * iterates stay on the affine set A w = b and do not reach it in practice,
+ * the one-CG-step variant and PALM with a growing xi can.               */
+#define L1_DIVERGED    3
 
 typedef enum { L1_P1 = 0, L1_P12 = 1, L1_QPLAMBDA = 2 } l1_problem;
 typedef enum { L1_DENSE = 0, L1_CAB = 1 } l1_structure;
@@ -97,6 +106,7 @@ typedef struct {
   int checkpoint_every;  /* checkpoint spacing in iterations (<= 0 -> 10)            */
   int time_kernels;      /* 1: time the DALM iteration loop with HIP events on the
                             solve stream (see l1_alm_last_stats)                    */
+  double div_factor;     /* L1_DIVERGED threshold factor (<= 0 -> 1e6)               */
 } l1_alm_desc;
 
 /* Build a plan for the dictionary A_dev (m x n_dict, column-major, leading
@@ -116,6 +126,12 @@ int l1_alm_plan(const l1_alm_desc* desc, const float* A_dev, void* stream,
 
 /* Solve N instances (columns of b_dev, m x N, leading dimension ldb >= m).
  *   eps_dev   P_{1,2}: N radii (device); NULL otherwise.
+ *   pen_dev   N per-instance penalties (device): beta for DALM, xi for PALM,
+ *             held constant for the whole solve; NULL takes desc.beta /
+ *             desc.xi, or the per-instance default when that is <= 0.  An
+ *             entry that is not positive and finite falls back to the
+ *             default of its instance.  Must be NULL for DALM on
+ *             QP_lambda (beta enters the factor there).
  *   tol       stopping tolerance: an instance stops after iteration k when
  *             ||w_k - w_{k-1}|| <= tol ||w_k|| and the complementarity gap of
  *             the l1 block | ||w||_1 - w^T A^T y | <= tol ||w||_1 (DALM), or
@@ -138,7 +154,7 @@ int l1_alm_plan(const l1_alm_desc* desc, const float* A_dev, void* stream,
  *   iters_dev, status_dev  N ints each (may be NULL).
  * n_full = n_dict + m for CAB and P_{1,2}, n_dict otherwise.             */
 int l1_alm_solve(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
-                 const float* eps_dev, float tol, int max_iter,
+                 const float* eps_dev, const float* pen_dev, float tol, int max_iter,
                  const float* w0_dev, const float* y0_dev,
                  float* x_dev, int ldx, float* e_dev, int lde,
                  float* y_dev, int ldy, int* iters_dev, int* status_dev,
@@ -150,7 +166,9 @@ int l1_alm_solve(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
  * gb (m x N, ld m, overwritten) = d<gx,x> + <ge,e> / d b and ADDS the
  * gradient with respect to the dictionary into gA (m x n_dict, ld m).
  * The iterations are recomputed segment by segment from checkpoints kept
- * every desc.checkpoint_every iterations.  beta is held constant.
+ * every desc.checkpoint_every iterations.  beta is held constant at the
+ * values the recorded solve used (pen_dev, or the default computed from
+ * b): the result is the gradient of the map with beta fixed.
  * Returns L1_ENOTAPE if no tape was recorded.                            */
 int l1_alm_backward(l1_alm_plan_t plan, const float* gx_dev, const float* ge_dev,
                     float* gb_dev, float* gA_dev, void* stream);

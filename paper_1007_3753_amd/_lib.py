@@ -2,9 +2,16 @@
 
 Loading fails loudly when the shared library has not been built: there is no
 fallback implementation of any step.
+
+Teardown: every live plan is registered here and destroyed by an ``atexit``
+hook, so the library releases its device memory while the HIP runtime and
+any profiler attached to it are still fully alive; a plan's ``__del__`` does
+nothing once the interpreter is finalizing.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libl1alm.so")
@@ -25,7 +32,7 @@ class l1_alm_desc(ctypes.Structure):
         ("xi_growth", ctypes.c_double), ("max_inner", ctypes.c_int),
         ("tol_inner", ctypes.c_double), ("refine_switch", ctypes.c_double),
         ("record_tape", ctypes.c_int), ("checkpoint_every", ctypes.c_int),
-        ("time_kernels", ctypes.c_int),
+        ("time_kernels", ctypes.c_int), ("div_factor", ctypes.c_double),
     ]
 
 
@@ -48,7 +55,7 @@ def load(path=LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i, f, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
     lib.l1_alm_plan.argtypes = [ctypes.POINTER(l1_alm_desc), vp, vp, ctypes.POINTER(vp)]
-    lib.l1_alm_solve.argtypes = [vp, vp, i, i, vp, f, i, vp, vp, vp, i, vp, i, vp, i, vp, vp, vp]
+    lib.l1_alm_solve.argtypes = [vp, vp, i, i, vp, vp, f, i, vp, vp, vp, i, vp, i, vp, i, vp, vp, vp]
     lib.l1_alm_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.l1_alm_kkt.argtypes = [vp, vp, i, i, vp, vp, i, vp, i, vp, i, vp, vp]
     lib.l1_alm_classify.argtypes = [vp, i, i, i, vp, i, vp, vp, vp, vp]
@@ -71,3 +78,31 @@ def check(rc):
     if rc != L1_OK:
         msg = _lib.l1_alm_last_error().decode(errors="replace")
         raise L1Error(rc, msg)
+
+
+# ---- deterministic teardown -------------------------------------------------
+_live = weakref.WeakSet()
+
+
+def register(obj):
+    """Track an object with a ``close()`` that releases library resources."""
+    _live.add(obj)
+
+
+def close_all():
+    """Close every live plan (also run at interpreter exit)."""
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    if _lib is not None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                torch.cuda.synchronize()
+        except Exception:
+            pass
+
+
+atexit.register(close_all)

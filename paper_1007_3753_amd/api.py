@@ -6,6 +6,7 @@ HIP stream are handed to the library, which runs every step of the method.
 PyTorch provides device memory and streams.
 """
 import ctypes
+import sys
 
 import torch
 
@@ -15,7 +16,7 @@ PROBLEMS = {"p1": 0, "p12": 1, "qp": 2}
 STRUCTURES = {"dense": 0, "cab": 1}
 METHODS = {"dalm": 0, "palm": 1, "dalm_cg1": 2}
 PRECISIONS = {"fp32": 0, "bf16_refine": 1, "bf16x3": 2}
-CONVERGED, MAXITER, NONFINITE = 0, 1, 2
+CONVERGED, MAXITER, NONFINITE, DIVERGED = 0, 1, 2, 3
 
 
 def _ptr(t):
@@ -56,7 +57,7 @@ class Plan:
     def __init__(self, A, *, problem="p1", structure="dense", method="dalm",
                  precision="fp32", max_batch=1, lam=0.0, beta=0.0, xi=0.0, xi_growth=1.0,
                  max_inner=100, tol_inner=0.0, refine_switch=0.0, record_tape=False,
-                 checkpoint_every=10, time_kernels=False):
+                 checkpoint_every=10, time_kernels=False, div_factor=0.0):
         self.lib = _lib.load()
         A = torch.as_tensor(A)
         if A.dim() != 2 or not A.is_cuda:
@@ -78,6 +79,7 @@ class Plan:
         d.max_inner, d.tol_inner, d.refine_switch = int(max_inner), float(tol_inner), float(refine_switch)
         d.record_tape, d.checkpoint_every = int(bool(record_tape)), int(checkpoint_every)
         d.time_kernels = int(bool(time_kernels))
+        d.div_factor = float(div_factor)
         self.desc = d
         self._tape_N = 0
         h = ctypes.c_void_p()
@@ -85,23 +87,37 @@ class Plan:
             Ac = torch.zeros(1, device=A.device)
         _lib.check(self.lib.l1_alm_plan(ctypes.byref(d), _ptr(Ac), _stream(), ctypes.byref(h)))
         self.handle = h
+        _lib.register(self)
 
     def close(self):
+        """Release the plan's device memory (idempotent)."""
         if getattr(self, "handle", None):
             self.lib.l1_alm_destroy(self.handle)
             self.handle = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # at interpreter shutdown the atexit hook of _lib has closed the plan
+        # already; never call into the library from a finalizing interpreter
+        if sys is None or sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
 
     def solve(self, b, *, tol=1e-6, max_iter=10000, eps=None, w0=None, y0=None,
-              want_y=True):
+              want_y=True, pen=None):
         """Solve the columns of ``b`` (m, N).  Returns SolveResult with
         x (n_dict, N), e (m, N) or None, y (m, N) or None, iters (N,), status (N,).
-        ``max_iter < 0`` runs exactly ``-max_iter`` iterations."""
+        ``max_iter < 0`` runs exactly ``-max_iter`` iterations.  ``pen``: N
+        per-instance penalties (DALM beta / PALM xi) held constant for the
+        solve, or None for the plan's setting."""
         bc = _colmajor(b, self.m)
         N = bc.shape[0]
         dev = bc.device
@@ -116,10 +132,17 @@ class Plan:
             epsc = torch.as_tensor(eps, dtype=torch.float32, device=dev).reshape(-1).contiguous()
             if epsc.numel() == 1 and N > 1:
                 epsc = epsc.expand(N).contiguous()
+        penc = None
+        if pen is not None:
+            penc = torch.as_tensor(pen, dtype=torch.float32, device=dev).reshape(-1).contiguous()
+            if penc.numel() == 1 and N > 1:
+                penc = penc.expand(N).contiguous()
+            if penc.numel() != N:
+                raise ValueError(f"pen must hold {N} values")
         w0c = _colmajor(w0, self.n_full) if w0 is not None else None
         y0c = _colmajor(y0, self.m) if y0 is not None else None
         _lib.check(self.lib.l1_alm_solve(
-            self.handle, _ptr(bc), self.m, N, _ptr(epsc), ctypes.c_float(tol), int(max_iter),
+            self.handle, _ptr(bc), self.m, N, _ptr(epsc), _ptr(penc), ctypes.c_float(tol), int(max_iter),
             _ptr(w0c), _ptr(y0c), _ptr(x), max(self.n_dict, 1), _ptr(e), self.m, _ptr(y), self.m,
             _ptr(iters), _ptr(status), _stream()))
         if max_iter < 0 and self.desc.record_tape:
@@ -260,21 +283,28 @@ def align(B, b, tol=1e-3, max_iter=1000, fixed_iters=None):
 
 
 class DALMUnrolled(torch.autograd.Function):
-    """``x, e = DALMUnrolled.apply(b, B, iters, checkpoint_every)``: exactly
-    ``iters`` dual ALM iterations (Algorithm 2) on the cross-and-bouquet
-    matrix [B, I] from w = 0, y = 0, as a differentiable map of b (m, N) and
-    B (m, n_B).  The forward solve and the backward pass both run in the
-    library (the backward recomputes the iterations from checkpoints kept
-    every ``checkpoint_every`` iterations); beta is the per-instance default
-    and is held constant."""
+    """``x, e = DALMUnrolled.apply(b, B, beta, iters, checkpoint_every)``:
+    exactly ``iters`` dual ALM iterations (Algorithm 2) on the
+    cross-and-bouquet matrix [B, I] from w = 0, y = 0, as a differentiable
+    map of b (m, N) and B (m, n_B) with the penalty ``beta`` (N values, or
+    one for all) an input held constant: the gradients are those of the map
+    at fixed beta (beta itself gets none).  The forward solve and the
+    backward pass both run in the library (the backward recomputes the
+    iterations from checkpoints kept every ``checkpoint_every``
+    iterations)."""
 
     @staticmethod
-    def forward(ctx, b, B, iters=50, checkpoint_every=10):
+    def forward(ctx, b, B, beta, iters=50, checkpoint_every=10):
         b = b.detach()
         B = B.detach()
+        beta = torch.as_tensor(beta, dtype=torch.float32, device=b.device).detach().reshape(-1)
+        if beta.numel() == 1:
+            beta = beta.expand(b.shape[1])
+        if beta.numel() != b.shape[1] or not bool(torch.all(beta > 0)):
+            raise ValueError("beta must hold one positive value per column of b (or one for all)")
         plan = Plan(B, structure="cab", precision="fp32", max_batch=b.shape[1],
                     record_tape=True, checkpoint_every=int(checkpoint_every))
-        r = plan.solve(b, max_iter=-int(iters), want_y=False)
+        r = plan.solve(b, max_iter=-int(iters), want_y=False, pen=beta)
         ctx.plan = plan
         return r.x, r.e
 
@@ -288,4 +318,4 @@ class DALMUnrolled(torch.autograd.Function):
         gb, gB = plan.backward(gx, ge)
         ctx.plan = None
         plan.close()
-        return gb, gB, None, None
+        return gb, gB, None, None, None

@@ -261,6 +261,7 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   p->ipen = dalloc<float>(Np, o);
   p->zscale = dalloc<float>(Np, o);
   p->tscal = dalloc<float>(Np * 4, o);
+  p->wcap2 = dalloc<float>(Np, o);
   const int ntiles = rows / TILE;
   p->ntiles = ntiles;
   p->partial = dalloc<float>((size_t)2 * ntiles * NPART * Np, o);  // two buffers
@@ -289,6 +290,7 @@ void destroy_plan(Plan* p) {
     if (w.second) (void)hipFree(w.second);
   for (void* q : p->tape) (void)hipFree(q);
   if (p->h_total) (void)hipHostFree(p->h_total);
+  tail_region_put(p->dev, p->tail_mem, p->tail_bytes);
   if (cur >= 0) (void)hipSetDevice(cur);
   delete p;
 }
@@ -324,14 +326,14 @@ int l1_alm_destroy(l1_alm_plan_t plan) {
 }
 
 int l1_alm_solve(l1_alm_plan_t plan, const float* b_dev, int ldb, int N, const float* eps_dev,
-                 float tol, int max_iter, const float* w0_dev, const float* y0_dev, float* x_dev,
-                 int ldx, float* e_dev, int lde, float* y_dev, int ldy, int* iters_dev,
-                 int* status_dev, void* stream) {
+                 const float* pen_dev, float tol, int max_iter, const float* w0_dev,
+                 const float* y0_dev, float* x_dev, int ldx, float* e_dev, int lde, float* y_dev,
+                 int ldy, int* iters_dev, int* status_dev, void* stream) {
   try {
     Plan* p = reinterpret_cast<Plan*>(plan);
     L1_REQUIRE(p != nullptr, "plan is NULL");
-    SolveArgs a{b_dev, ldb, N, eps_dev, tol, max_iter, w0_dev, y0_dev, x_dev, ldx, e_dev, lde,
-                y_dev, ldy, iters_dev, status_dev, reinterpret_cast<hipStream_t>(stream)};
+    SolveArgs a{b_dev, ldb, N, eps_dev, pen_dev, tol, max_iter, w0_dev, y0_dev, x_dev, ldx, e_dev,
+                lde, y_dev, ldy, iters_dev, status_dev, reinterpret_cast<hipStream_t>(stream)};
     if (p->d.method == L1_DALM) solve_dalm(p, a);
     else if (p->d.method == L1_PALM) solve_palm(p, a);
     else solve_dalm_cg1(p, a);
@@ -460,7 +462,16 @@ int l1_alm_tune_ksplit(l1_alm_plan_t plan, int iters, int* ks_out, int n, void* 
   int* it = nullptr;
   int* st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // the tuner's solves must neither replace the plan's recorded tape nor
+  // leave a trial split in the table when they fail
+  Plan* pp = reinterpret_cast<Plan*>(plan);
+  int saved_tape = 0, saved_ks[9] = {0};
+  bool saved = false;
   auto release = [&]() {
+    if (saved) {
+      pp->d.record_tape = saved_tape;
+      std::memcpy(pp->ks_table, saved_ks, sizeof(saved_ks));
+    }
     if (b) (void)hipFree(b);
     if (x) (void)hipFree(x);
     if (it) (void)hipFree(it);
@@ -475,6 +486,10 @@ int l1_alm_tune_ksplit(l1_alm_plan_t plan, int iters, int* ks_out, int n, void* 
     L1_REQUIRE(iters >= 16 && iters <= 4096, "iters must be in [16, 4096]");
     L1_REQUIRE(n >= 0 && n <= L1_KSPLIT_TILES && (n == 0 || ks_out != nullptr), "bad table");
     L1_REQUIRE(p->d.problem != L1_P12, "tuning runs (P1) and (QP_lambda) plans");
+    saved_tape = p->d.record_tape;
+    std::memcpy(saved_ks, p->ks_table, sizeof(saved_ks));
+    saved = true;
+    p->d.record_tape = 0;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int m = p->m, nd = std::max(p->nd, 1);
     const int tmax = std::min(L1_KSPLIT_TILES, p->d.max_batch / TILE);
@@ -500,10 +515,11 @@ int l1_alm_tune_ksplit(l1_alm_plan_t plan, int iters, int* ks_out, int n, void* 
     // can take over there (it runs the parts the heuristic gives it); when
     // its workgroups could not hold the operator rows it never runs, and the
     // one-tile shape is tuned too
-    const bool tail_possible = p->n_pad / TAIL_ROWS <= 16 * TAIL_TG;
+    const int phases_used = p->d.precision == L1_BF16_REFINE ? 2 : 1;
+    const bool tail_possible = tail_fits(p->n_pad, p->ntiles, std::min(dalm_ksplit(p, 1, phases_used), 8));
     for (int t = tail_possible ? 2 : 1; t <= tmax; ++t) {
       const int N = t * TILE;
-      SolveArgs a{b, m, N, nullptr, 0.0f, -iters, nullptr, nullptr, x, nd, nullptr, 0,
+      SolveArgs a{b, m, N, nullptr, nullptr, 0.0f, -iters, nullptr, nullptr, x, nd, nullptr, 0,
                   nullptr, 0, it, st, s};
       float best = 0.0f;
       int best_ks = 0;
@@ -527,6 +543,8 @@ int l1_alm_tune_ksplit(l1_alm_plan_t plan, int iters, int* ks_out, int n, void* 
       p->ks_table[t] = best_ks;
     }
     for (int t = 1; t <= n; ++t) ks_out[t - 1] = p->ks_table[t];
+    // keep the tuned table; restore only the tape flag
+    std::memcpy(saved_ks, p->ks_table, sizeof(saved_ks));
     release();
     return L1_OK;
   } catch (const Fail& f) {

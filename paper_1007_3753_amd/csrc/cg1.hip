@@ -91,7 +91,8 @@ __global__ __launch_bounds__(CG_THREADS) void cg1_update_kernel(int m, int m_pad
                                                                 int lds, float tol, int fixed, int* state,
                                                                 int* iters, int* status, const float* H,
                                                                 const float* G, const double* gg,
-                                                                const float* Z, const float* pen, float* W,
+                                                                const float* Z, const float* pen,
+                                                                const float* wcap2, float* W,
                                                                 float* V, float* Y) {
   __shared__ double red[CG_THREADS];
   const int j = blockIdx.x, tid = threadIdx.x;
@@ -128,6 +129,9 @@ __global__ __launch_bounds__(CG_THREADS) void cg1_update_kernel(int m, int m_pad
     const double gap = fabs(wl1 - wv);
     if (!(isfinite(nw2) && isfinite(gap))) {
       status[j] = L1_NONFINITE;
+      state[j] = 2;
+    } else if (!fixed && nw2 > (double)wcap2[j]) {
+      status[j] = L1_DIVERGED;
       state[j] = 2;
     } else if (!fixed && sqrt(dw2) <= (double)tol * sqrt(nw2) && gap <= (double)tol * wl1) {
       status[j] = L1_CONVERGED;
@@ -213,7 +217,8 @@ void solve_dalm_cg1(Plan* p, const SolveArgs& sa) {
   L1_HIP(hipMemsetAsync(p->bb, 0, sizeof(float) * ldm * N, s));
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * ldm, sa.b, sizeof(float) * sa.ldb, sizeof(float) * m, N,
                           hipMemcpyDeviceToDevice, s));
-  penalties(s, N, m, p->bb, ldm, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0, p->pen, p->ipen);
+  penalties(s, N, m, p->bb, ldm, sa.pen, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0, div_factor(p),
+            p->pen, p->ipen, p->wcap2);
   L1_HIP(hipMemsetAsync(p->W, 0, sizeof(float) * (size_t)lds * N, s));
   L1_HIP(hipMemsetAsync(p->V, 0, sizeof(float) * (size_t)lds * N, s));
   L1_HIP(hipMemsetAsync(U, 0, sizeof(float) * (size_t)lds * N, s));
@@ -260,7 +265,7 @@ void solve_dalm_cg1(Plan* p, const SolveArgs& sa) {
     L1_HIP(hipGetLastError());
     if (nd > 0) launch_gemm(s, EPI_STORE, g2, ntc);
     cg1_update_kernel<<<N, CG_THREADS, 0, s>>>(m, ldm, nd, n, cab, lds, t_eff, fixed ? 1 : 0, state, iters,
-                                               status, H, G, gg, p->Z[0], p->pen, p->W, p->V, Y);
+                                               status, H, G, gg, p->Z[0], p->pen, p->wcap2, p->W, p->V, Y);
     L1_HIP(hipGetLastError());
     ++it;
     if (!fixed && (it % kPoll == 0 || it == cap)) {

@@ -11,6 +11,7 @@ struct TestParams {
   float floor[NPHASE];   // the final test uses max(tol, floor[phase])
   float sw;              // exit threshold of a non-final phase
   int final_phase;
+  float wcap2;           // ||w||^2 above this: L1_DIVERGED (with tol >= 0 only)
 };
 
 // Sums of the per-row-tile partials of column c, taken by 4 cooperating lanes
@@ -42,6 +43,10 @@ __device__ inline int decide(const TestParams& tp, int st, const float (&sm)[NPA
   const float d2 = sm[0], w2 = sm[1], l1 = sm[2], gap = fabsf(sm[3]);
   if (!(isfinite(d2) && isfinite(w2) && isfinite(gap))) {
     *status = L1_NONFINITE;
+    return NPHASE;
+  }
+  if (tp.tol >= 0.0f && w2 > tp.wcap2) {
+    *status = L1_DIVERGED;
     return NPHASE;
   }
   if (st != tp.final_phase) {

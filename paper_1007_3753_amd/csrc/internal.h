@@ -151,6 +151,7 @@ struct GemmArgs {
   int tp_final;
   int test_kind;               // 0: DALM test (decide()), 1: FISTA inner test (relative change)
   const float* eps;            // P_{1,2} radii (the ball scale comes from prev_partial)
+  const float* wcap2;          // squared L1_DIVERGED thresholds per column (null: none)
   long long* stat;             // [3 + prec] += live columns, [prec] += column tiles
 };
 

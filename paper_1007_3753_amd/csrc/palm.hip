@@ -64,6 +64,7 @@ struct PalmArgs {
   uint16_t* Zlo;
   float* xi;            // penalty per instance
   const float* eps;     // P_{1,2} radii
+  const float* wcap2;   // squared L1_DIVERGED thresholds
   int* state;           // 0 active, NPHASE finished (outer loop)
   int* inner_state[2];  // inner-loop phase buffers: reset to `phase` for active instances
   int phase;            // phase index of the inner products
@@ -168,6 +169,9 @@ __global__ __launch_bounds__(256) void palm_update_kernel(PalmArgs a) {
     if (!(isfinite(dw) && isfinite(nw) && isfinite(rr))) {
       a.state[c] = NPHASE;
       a.status[c] = L1_NONFINITE;
+    } else if (a.tol >= 0.0f && nw > a.wcap2[c]) {
+      a.state[c] = NPHASE;
+      a.status[c] = L1_DIVERGED;
     } else if (a.tol >= 0.0f && dw <= a.tol * a.tol * nw && rr <= a.tol * a.tol * bb) {
       a.state[c] = NPHASE;
       a.status[c] = L1_CONVERGED;
@@ -330,7 +334,8 @@ void solve_palm(Plan* p, const SolveArgs& sa) {
   L1_HIP(hipMemsetAsync(p->bb, 0, sizeof(float) * ldm * N, s));
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * ldm, sa.b, sizeof(float) * sa.ldb,
                           sizeof(float) * m, N, hipMemcpyDeviceToDevice, s));
-  penalties(s, N, m, p->bb, ldm, p->d.xi > 0 ? (float)p->d.xi : 0.0f, 1, p->pen, p->ipen);
+  penalties(s, N, m, p->bb, ldm, sa.pen, p->d.xi > 0 ? (float)p->d.xi : 0.0f, 1, div_factor(p),
+            p->pen, p->ipen, p->wcap2);
   float* eps = nullptr;
   if (p->d.problem == L1_P12) {
     eps = p->tscal;
@@ -367,6 +372,7 @@ void solve_palm(Plan* p, const SolveArgs& sa) {
   pa.Zlo = low ? p->Ul[0] : nullptr;
   pa.xi = p->pen;
   pa.eps = eps;
+  pa.wcap2 = p->wcap2;
   pa.state = state;
   pa.inner_state[0] = inner_st[0];
   pa.inner_state[1] = inner_st[1];

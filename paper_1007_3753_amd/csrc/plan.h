@@ -42,6 +42,7 @@ struct Plan {
   float* ipen = nullptr;  // its reciprocal
   float* zscale = nullptr;
   float* tscal = nullptr;
+  float* wcap2 = nullptr; // per instance: squared L1_DIVERGED threshold on ||w||_2
   float* partial = nullptr;
   float* ws = nullptr;    // split-K workspace: ws_tiles x TILE x lds floats
   int ws_tiles = 0, ks_target = 192, ks_max = 4;
@@ -52,6 +53,11 @@ struct Plan {
   long long* stat = nullptr;
   double* kkt_rbuf = nullptr;
   int* h_total = nullptr; // pinned
+  // the tail kernel's uncached exchange region (barrier, flags, u and
+  // partial sums), owned by this plan and given back to the device's free
+  // list when it is destroyed
+  void* tail_mem = nullptr;
+  size_t tail_bytes = 0;
   double last_stats[14] = {0};
   double plan_ms = 0.0;
   // tape of the last recorded fixed-count solve
@@ -74,6 +80,7 @@ struct SolveArgs {
   int ldb;
   int N;
   const float* eps;
+  const float* pen;   // per-instance penalties or null
   float tol;
   int max_iter;
   const float* w0;
@@ -88,6 +95,11 @@ struct SolveArgs {
   int* status;
   hipStream_t s;
 };
+
+// L1_DIVERGED threshold factor of the plan (desc.div_factor, default 1e6)
+inline float div_factor(const Plan* p) {
+  return p->d.div_factor > 0 ? (float)p->d.div_factor : 1e6f;
+}
 
 Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s);
 void destroy_plan(Plan* p);

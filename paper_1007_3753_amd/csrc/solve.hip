@@ -64,6 +64,8 @@ void check_common(Plan* p, const SolveArgs& a) {
   L1_REQUIRE(p->d.problem != L1_P12 || a.eps != nullptr, "P_{1,2} needs eps (N radii)");
   L1_REQUIRE(a.max_iter != 0, "max_iter must be nonzero");
   L1_REQUIRE(std::isfinite(a.tol) && a.tol >= 0.0f, "tol must be finite and >= 0");
+  L1_REQUIRE(!(a.pen && p->d.problem == L1_QPLAMBDA && p->d.method == L1_DALM),
+             "DALM on QP_lambda takes beta from the plan (it enters the factor): pen must be NULL");
 }
 
 }  // namespace
@@ -117,8 +119,8 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   L1_HIP(hipMemsetAsync(p->bb, 0, sizeof(float) * p->m_pad * N, s));
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * p->m_pad, a.b, sizeof(float) * a.ldb,
                           sizeof(float) * m, N, hipMemcpyDeviceToDevice, s));
-  penalties(s, N, m, p->bb, p->m_pad, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0, p->pen,
-            p->ipen);
+  penalties(s, N, m, p->bb, p->m_pad, a.pen, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0,
+            div_factor(p), p->pen, p->ipen, p->wcap2);
   {
     GemmArgs g{};
     g.A32 = p->Cop;
@@ -243,6 +245,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   for (int q = 0; q < NPHASE; ++q) it.tp_floor[q] = floors[q];
   it.tp_final = last;
   it.eps = p12 ? eps : nullptr;
+  it.wcap2 = p->wcap2;
   it.stat = p->stat;
   it.ws = p->ws;
   DalmCheck ck{};
@@ -257,6 +260,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   ck.L = L;
   ck.eps = eps;
   ck.beta = p->pen;
+  ck.wcap2 = p->wcap2;
   ck.stat = p->stat;
   P12Fix fx{};
   fx.n = n;
@@ -421,10 +425,16 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
       if (tail_ok && done > 0 && done >= tail_retry && active <= tail_cap) {
         retire();
         const int G = p->n_pad / TAIL_ROWS;
-        const size_t xu = (size_t)TAIL_NC * p->n_pad * 2;
-        const size_t xp = (size_t)G * NPART * TAIL_NC * 4;
-        const size_t need = 256 + 4 * xu + 2 * xp + 1024;
-        unsigned char* pool = reinterpret_cast<unsigned char*>(tail_pool(need));
+        // tagged 8-byte words: u [TAIL_NC][n_pad] and partial sums
+        // [G][NPART][TAIL_NC], two of each; flags in the first 256 bytes
+        const size_t xu = (size_t)TAIL_NC * p->n_pad * 8;
+        const size_t xp = (size_t)G * NPART * TAIL_NC * 8;
+        const size_t need = 256 + 2 * xu + 2 * xp;
+        if (p->tail_bytes < need) {
+          tail_region_put(p->dev, p->tail_mem, p->tail_bytes);
+          p->tail_mem = tail_region_get(need, &p->tail_bytes);
+        }
+        unsigned char* pool = reinterpret_cast<unsigned char*>(p->tail_mem);
         if (!pool) {
           tail_ok = false;
         } else {
@@ -441,6 +451,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           ta.W = p->W;
           ta.C = p->C;
           ta.beta = p->pen;
+          ta.wcap2 = p->wcap2;
           ta.st[0] = stbuf[0];
           ta.st[1] = stbuf[1];
           ta.iters = L.iters;
@@ -460,21 +471,20 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           for (int q = 0; q < NPHASE; ++q) ta.tp.floor[q] = floors[q];
           unsigned char* c = pool + 256;
           for (int b = 0; b < 2; ++b) {
-            if (tail_f32) ta.xu32[b] = reinterpret_cast<float*>(c);
-            else ta.xpk[b] = reinterpret_cast<uint32_t*>(c);
-            c += 2 * xu;   // [TAIL_NC][n_pad] words of 4 bytes
+            ta.xu[b] = reinterpret_cast<unsigned long long*>(c);
+            c += xu;
           }
           for (int b = 0; b < 2; ++b) {
-            ta.xpart[b] = reinterpret_cast<float*>(c);
+            ta.xpart[b] = reinterpret_cast<unsigned long long*>(c);
             c += xp;
           }
-          ta.bar = reinterpret_cast<unsigned*>(pool);
           ta.flag = reinterpret_cast<int*>(pool + 64);
           ta.k0 = done;
           ta.k_end = cap;
           ta.ks = std::min(sh.ks, 8);
           ta.stat = p->stat;
-          L1_HIP(hipMemsetAsync(pool, 0, 256, s));
+          // no tag of an earlier launch may match: clear flags and words
+          L1_HIP(hipMemsetAsync(pool, 0, need, s));
           if (timing) L1_HIP(hipEventRecord(ev[0], s));
           if (launch_dalm_tail(s, ta)) {
             if (timing) L1_HIP(hipEventRecord(ev[1], s));

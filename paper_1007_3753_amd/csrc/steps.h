@@ -46,6 +46,7 @@ struct DalmCheck {
   int* state_other;      // the other phase buffer (compaction copies into it)
   const float* eps;      // P_{1,2} radii
   const float* beta;
+  const float* wcap2;    // squared L1_DIVERGED thresholds (null: no test)
   long long* stat;       // [7] = largest per-instance iteration count
 };
 
@@ -64,8 +65,11 @@ struct P12Fix {
   uint16_t* Ulo;
 };
 
-void penalties(hipStream_t s, int N, int m, const float* b, int ldb, float fixed, int mode,
-               float* pen, float* ipen);
+// Per-instance penalty (mode 0: DALM beta, 1: PALM xi) from pen_in[c] when it
+// is positive and finite, else `fixed` when > 0, else the default of the
+// instance; and the squared L1_DIVERGED threshold (div sqrt(m) ||b||_2)^2.
+void penalties(hipStream_t s, int N, int m, const float* b, int ldb, const float* pen_in,
+               float fixed, int mode, float div, float* pen, float* ipen, float* wcap2);
 void dalm_init_u(hipStream_t s, int N, const DalmInit& a);
 void init_lists(hipStream_t s, int N, int phase0, const Lists& L, int* state_other,
                 long long* stat);

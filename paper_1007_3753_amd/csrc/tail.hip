@@ -12,18 +12,25 @@
 //     iteration GEMM splits it (MFMA, parts added in a fixed order), applies
 //     the dual ALM update of Algorithm 2 (the same arithmetic as the epilogue
 //     of the iteration GEMM), and publishes its rows of the next u and its
-//     partial sums;
-//   - one grid barrier per iteration; the next iteration starts with the
-//     convergence test of this one (every workgroup computes it, so all take
-//     the same decisions).
-// Published data are written and read with agent-scope (sc1) accesses, which
-// the memory system keeps coherent across the XCDs' L2 caches, so the barrier
-// needs no L2 writeback or invalidation: each wave waits for its own stores,
-// the workgroup adds to a counter and waits (bounded) for the grid, then the
-// compute unit's L1 is dropped.
+//     partial sums; the next iteration starts with the convergence test of
+//     this one (every workgroup computes it from the same sums, so all take
+//     the same decisions and leave at the same iteration).
+// Exchange without a grid barrier: every published 32-bit value travels in
+// one 64-bit word with a tag, the index of the iteration that consumes it
+// plus one, written and read as single 64-bit agent-scope atomics (which the
+// memory system keeps coherent across the XCDs' L2 caches).  A consumer
+// polls until every word it needs carries the tag it expects, so the data
+// and its readiness arrive in the same memory round trip.  Two buffers by
+// iteration parity make the reuse safe: a workgroup can write the buffer of
+// iteration k + 1 only after it has read every row of iteration k, which the
+// other workgroups publish only after they have finished reading iteration
+// k - 1 from that same buffer.  The exchange memory is cleared before every
+// launch, so no stale tag can match.  Every wait is bounded: a workgroup that
+// gives up raises a flag that ends the others' waits too.
 #include <algorithm>
 #include <mutex>
 
+#include "region_list.h"
 #include "tail.h"
 
 namespace l1 {
@@ -66,32 +73,14 @@ __device__ inline void stfc(float* p, float v) {
 __device__ inline int ldu32(int n_pad) { return n_pad + 4; }
 __device__ inline int ldu16(int n_pad) { return n_pad + 8; }
 
-// grid barrier on a counter in device memory; false if it gave up
-__device__ inline bool tail_sync(unsigned* bar, unsigned target, int* flag) {
-  __shared__ int s_ok;
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicAdd(bar, 1u);
-    int ok = 1;
-    unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-          ++spins > (1u << 20)) {
-        atomicExch(flag, 1);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    // drop this compute unit's vector L1 so the next loads of published data
-    // (and of this workgroup's own rows) come from memory
-    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
-    s_ok = ok;
-  }
-  __syncthreads();
-  return s_ok != 0;
+__device__ inline unsigned long long tagged(uint32_t v, unsigned tag) {
+  return (unsigned long long)v | ((unsigned long long)tag << 32);
 }
+__device__ inline void st8c(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// polls of one wait before a workgroup gives up (each after a short sleep)
+constexpr unsigned TAIL_SPIN_LIMIT = 1u << 20;
 
 }  // namespace
 
@@ -102,6 +91,8 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
   __shared__ float s_red[8][16][17];
   __shared__ float s_ps[NPART][16][TAIL_NC];
   __shared__ float s_ts[TAIL_NC][16][NPART];
+  // the partial sums of the previous iteration, [instance][sum][row group]
+  __shared__ float s_pp[TAIL_NC][NPART][16 * TAIL_TG];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, q = lane >> 4;
   const int g = blockIdx.x, G = gridDim.x;
@@ -175,88 +166,167 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
   const float bt = eown ? a.beta[s_col[ej]] : 1.0f;
   const float ib = 1.0f / bt;
 
-  unsigned gen = 0;
+  __shared__ int s_gaveup;
+  if (tid == 0) s_gaveup = 0;
   int k = a.k0;
   for (;; ++k) {
     const bool first = (k == a.k0);
+    const unsigned want = (unsigned)k + 1u;   // tag of the words iteration k consumes
     // ---- loads: u of iteration k and the partial sums of iteration k - 1 ------
     // every load of the phase is issued before the first is used (one memory
-    // round trip): a thread moves at most TAIL_UV 16-byte vectors of u and
-    // sums at most TAIL_TG groups of partial sums
+    // round trip when the data is ready): a thread moves at most TAIL_UV
+    // 16-byte vectors of u and sums at most TAIL_TG groups of partial sums.
+    // Only instances still running published u (the others' columns of the
+    // stage keep stale values whose products are never used).
     const int tj = tid >> 4, sub = tid & 15;
     {
-      const int nv = n_pad / 4;   // 16-byte vectors per instance (FP32, or hi + lo BF16)
+      // 16-byte vectors per instance: the launch path's FP32 or hi / lo
+      // split layout (4 values), or two tagged words (2 values); staged in
+      // rounds of TAIL_UR vectors per thread (registers), the partial sums
+      // with the first round
+      const int nv = first ? n_pad / 4 : n_pad / 2;
       const int nvec = nc * nv;
-      u4 uv[TAIL_UV];
-#pragma unroll
-      for (int i = 0; i < TAIL_UV; ++i) {
-        const int e = tid + 256 * i;
-        if (e < nvec) {
-          const int j = e / nv, w = e % nv;
-          const void* src;
-          if (F32) {
-            src = first ? (const void*)(a.U32 + (long)s_col[j] * a.lds + w * 4)
-                        : (const void*)(a.xu32[k & 1] + (long)j * n_pad + w * 4);
-          } else if (first) {
-            // the launch path's split: the first half of an instance's
-            // vectors are hi, the second lo
-            const int hl = w >= nv / 2, w8 = (w - hl * (nv / 2)) * 8;
-            src = (hl ? a.Ulo : a.Uhi) + (long)s_col[j] * a.lds + w8;
-          } else {
-            // packed words: vector w holds elements 4w .. 4w + 3
-            src = a.xpk[k & 1] + (long)j * n_pad + w * 4;
-          }
-          uv[i] = first ? ld16(src) : ld16c(src);
+      const int nt = first ? a.ntiles : G;
+      const unsigned long long* xu = a.xu[k & 1];
+      const unsigned long long* xp = a.xpart[(k - 1) & 1];
+      auto u_src_ok = [&](int e) { return e < nvec && s_st[e / nv] < NPHASE; };
+      auto load_u = [&](int e) -> u4 {
+        const int j = e / nv, w = e % nv;
+        if (F32 && first) return ld16(a.U32 + (long)s_col[j] * a.lds + w * 4);
+        if (first) {
+          // the launch path's split: the first half of an instance's
+          // vectors are hi, the second lo
+          const int hl = w >= nv / 2, w8 = (w - hl * (nv / 2)) * 8;
+          return ld16((hl ? a.Ulo : a.Uhi) + (long)s_col[j] * a.lds + w8);
         }
-      }
-      float tv[TAIL_TG][NPART];
-      const bool tlive = tj < nc && s_st[tj] < NPHASE;
+        return ld16c(xu + (long)j * n_pad + w * 2);
+      };
+      // partial sums: element f = (j NPART + p) 128 + t of [instance j][sum
+      // p][row group t], TAIL_PR per thread, spread over the workgroup
+      constexpr int PT = 16 * TAIL_TG;
+      auto p_ok = [&](int f) {
+        const int t = f % PT, jp = f / PT, j = jp / NPART;
+        return j < nc && s_st[j] < NPHASE && t < nt;
+      };
+      auto p_addr = [&](int f) -> long {
+        const int t = f % PT, jp = f / PT, j = jp / NPART, p = jp % NPART;
+        return ((long)t * NPART + p) * TAIL_NC + j;
+      };
+      float pv[TAIL_PR];
+      unsigned pstale = 0;   // partial sums still carrying an old tag
 #pragma unroll
-      for (int i = 0; i < TAIL_TG; ++i) {
-        const int t = sub + 16 * i;
-        const int nt = first ? a.ntiles : G;
+      for (int round = 0; round < TAIL_UV / TAIL_UR; ++round) {
+        if (round > 0 && 256 * TAIL_UR * round >= nvec) break;
+        u4 uv[TAIL_UR];
+        unsigned ustale = 0;
 #pragma unroll
-        for (int p = 0; p < NPART; ++p) {
-          float v = 0.0f;
-          if (tlive && t < nt) {
-            v = first ? a.reg_partial[((long)t * NPART + p) * a.ldp + s_col[tj]]
-                      : ldfc(a.xpart[(k - 1) & 1] + ((long)t * NPART + p) * TAIL_NC + tj);
-          }
-          tv[i][p] = v;
+        for (int i = 0; i < TAIL_UR; ++i) {
+          const int e = tid + 256 * (TAIL_UR * round + i);
+          if (u_src_ok(e)) uv[i] = load_u(e);
         }
-      }
+        if (round == 0) {
 #pragma unroll
-      for (int i = 0; i < TAIL_UV; ++i) {
-        const int e = tid + 256 * i;
-        if (e < nvec) {
+          for (int i = 0; i < TAIL_PR; ++i) {
+            const int f = tid + 256 * i;
+            pv[i] = 0.0f;
+            if (p_ok(f)) {
+              if (first) {
+                const int t = f % PT, jp = f / PT;
+                pv[i] = a.reg_partial[((long)t * NPART + jp % NPART) * a.ldp + s_col[jp / NPART]];
+              } else {
+                const unsigned long long v = ld8c(xp + p_addr(f));
+                pv[i] = __uint_as_float((uint32_t)v);
+                if ((unsigned)(v >> 32) != want) pstale |= 1u << i;
+              }
+            }
+          }
+        }
+        if (!first) {
+#pragma unroll
+          for (int i = 0; i < TAIL_UR; ++i) {
+            const int e = tid + 256 * (TAIL_UR * round + i);
+            if (u_src_ok(e) && (uv[i][1] != want || uv[i][3] != want)) ustale |= 1u << i;
+          }
+          // poll until every word this thread needs carries the expected tag
+          unsigned spins = 0;
+          while (ustale | pstale) {
+            if (++spins > TAIL_SPIN_LIMIT ||
+                __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              atomicExch(a.flag, 1);
+              s_gaveup = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+            for (int i = 0; i < TAIL_UR; ++i) {
+              if (ustale & (1u << i)) {
+                uv[i] = load_u(tid + 256 * (TAIL_UR * round + i));
+                if (uv[i][1] == want && uv[i][3] == want) ustale &= ~(1u << i);
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < TAIL_PR; ++i)
+              if (pstale & (1u << i)) {
+                const unsigned long long v = ld8c(xp + p_addr(tid + 256 * i));
+                pv[i] = __uint_as_float((uint32_t)v);
+                if ((unsigned)(v >> 32) == want) pstale &= ~(1u << i);
+              }
+          }
+          if (ustale | pstale) break;   // gave up
+        }
+#pragma unroll
+        for (int i = 0; i < TAIL_UR; ++i) {
+          const int e = tid + 256 * (TAIL_UR * round + i);
+          if (!u_src_ok(e)) continue;
           const int j = e / nv, w = e % nv;
-          if (F32) {
-            *reinterpret_cast<u4*>(reinterpret_cast<float*>(ustage) + (long)j * ldu32(n_pad) + w * 4) = uv[i];
-          } else if (first) {
-            const int hl = w >= nv / 2, w8 = (w - hl * (nv / 2)) * 8;
-            uint16_t* sh = reinterpret_cast<uint16_t*>(ustage) + (long)(hl * ncap + j) * ldu16(n_pad);
-            *reinterpret_cast<u4*>(sh + w8) = uv[i];
-          } else {
-            // unpack four (hi, lo) words into four hi and four lo values
-            const u4 v = uv[i];
+          if (first) {
+            if (F32) {
+              *reinterpret_cast<u4*>(reinterpret_cast<float*>(ustage) + (long)j * ldu32(n_pad) + w * 4) = uv[i];
+            } else {
+              const int hl = w >= nv / 2, w8 = (w - hl * (nv / 2)) * 8;
+              uint16_t* sh = reinterpret_cast<uint16_t*>(ustage) + (long)(hl * ncap + j) * ldu16(n_pad);
+              *reinterpret_cast<u4*>(sh + w8) = uv[i];
+            }
+          } else if (F32) {
+            // two tagged FP32 values: elements 2w, 2w + 1
             typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-            const u2 hi = {(v[0] & 0xffffu) | (v[1] << 16), (v[2] & 0xffffu) | (v[3] << 16)};
-            const u2 lo = {(v[0] >> 16) | (v[1] & 0xffff0000u), (v[2] >> 16) | (v[3] & 0xffff0000u)};
-            uint16_t* sh = reinterpret_cast<uint16_t*>(ustage) + (long)j * ldu16(n_pad) + w * 4;
-            *reinterpret_cast<u2*>(sh) = hi;
-            *reinterpret_cast<u2*>(sh + (long)ncap * ldu16(n_pad)) = lo;
+            *reinterpret_cast<u2*>(reinterpret_cast<float*>(ustage) + (long)j * ldu32(n_pad) + w * 2) =
+                u2{uv[i][0], uv[i][2]};
+          } else {
+            // two tagged (hi | lo << 16) words: the hi pair and the lo pair
+            // of elements 2w, 2w + 1
+            const uint32_t hi = (uv[i][0] & 0xffffu) | (uv[i][2] << 16);
+            const uint32_t lo = (uv[i][0] >> 16) | (uv[i][2] & 0xffff0000u);
+            uint16_t* sh = reinterpret_cast<uint16_t*>(ustage) + (long)j * ldu16(n_pad) + w * 2;
+            *reinterpret_cast<uint32_t*>(sh) = hi;
+            *reinterpret_cast<uint32_t*>(sh + (long)ncap * ldu16(n_pad)) = lo;
           }
         }
       }
+#pragma unroll
+      for (int i = 0; i < TAIL_PR; ++i) {
+        const int f = tid + 256 * i;
+        const int t = f % PT, jp = f / PT;
+        if (jp < nc * NPART) s_pp[jp / NPART][jp % NPART][t] = pv[i];
+      }
+    }
+    __syncthreads();
+    if (s_gaveup) return;
+    // per instance and sum, 16 threads add the row groups t = sub + 16 i
+    {
+      const bool tlive = tj < nc && s_st[tj] < NPHASE;
 #pragma unroll
       for (int p = 0; p < NPART; ++p) {
         float v = 0.0f;
+        if (tlive) {
 #pragma unroll
-        for (int i = 0; i < TAIL_TG; ++i) v += tv[i][p];
+          for (int i = 0; i < TAIL_TG; ++i) v += s_pp[tj][p][sub + 16 * i];
+        }
         s_ts[tj][sub][p] = v;
       }
     }
     __syncthreads();
+    if (s_gaveup) return;
 
     // ---- convergence test of iteration k - 1 (the same in every workgroup) ----
     if (tid < TAIL_NC) {
@@ -273,7 +343,9 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
         // the first sums come from the launch-per-iteration path, whose
         // product may have run in a lower arithmetic than the final phase
         const int ar = (first && a.reg_arith) ? a.reg_arith[s_col[j]] : NPHASE;
-        const int st = decide_in(a.tp, s_st[j], ar, sm, &stat_new);
+        TestParams tp = a.tp;
+        tp.wcap2 = a.wcap2 ? a.wcap2[s_col[j]] : INFINITY;
+        const int st = decide_in(tp, s_st[j], ar, sm, &stat_new);
         if (g == 0) {
           if (st >= NPHASE) a.status[s_col[j]] = stat_new;
           else if (k < a.k_end) a.iters[s_col[j]] += 1;
@@ -367,14 +439,15 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
         const float un = z2 - wn * ib;
         vreg = vn;
         wreg = wn;
+        // the next u, tagged for iteration k + 1
         const long xo = (long)ej * n_pad + rw;
-        const int nb = (k + 1) & 1;
+        const unsigned tag = (unsigned)k + 2u;
         if (F32) {
-          stfc(a.xu32[nb] + xo, un);
+          st8c(a.xu[(k + 1) & 1] + xo, tagged(__float_as_uint(un), tag));
         } else {
           const uint16_t h = f2bf_t(un);
           const uint32_t w = (uint32_t)h | ((uint32_t)f2bf_t(un - bf2f_t(h)) << 16);
-          __hip_atomic_store(a.xpk[nb] + xo, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          st8c(a.xu[(k + 1) & 1] + xo, tagged(w, tag));
         }
         const float d = wn - wo;
         part[0] = d * d;
@@ -393,9 +466,8 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
       const int p = tid / TAIL_NC, j = tid % TAIL_NC;
       float sum = 0.0f;
       for (int r = 0; r < 16; ++r) sum += s_ps[p][r][j];
-      stfc(a.xpart[k & 1] + ((long)g * NPART + p) * TAIL_NC + j, sum);
+      st8c(a.xpart[k & 1] + ((long)g * NPART + p) * TAIL_NC + j, tagged(__float_as_uint(sum), (unsigned)k + 2u));
     }
-    if (!tail_sync(a.bar, (unsigned)G * ++gen, a.flag)) return;
   }
   // v and w back to memory; final phases into both buffers; iteration count
   if (eown) {
@@ -412,25 +484,33 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
 }
 
 int tail_capacity(int n_pad, int f32) {
-  const size_t budget = 128 * 1024;   // LDS for the u stage
+  const size_t budget = 96 * 1024;    // LDS for the u stage
   const size_t per_col = f32 ? (size_t)(n_pad + 4) * 4 : (size_t)(n_pad + 8) * 2 * 2;
-  const size_t by_loads = (size_t)256 * TAIL_UV / (size_t)(n_pad / 4);   // u vectors per thread
-  return (int)std::min<size_t>({(size_t)TAIL_NC, budget / per_col, by_loads});
+  const size_t by_loads = (size_t)256 * TAIL_UV / (size_t)(n_pad / 2);   // tagged u vectors per thread
+  const size_t by_sums = (size_t)256 * TAIL_PR / (size_t)(NPART * 16 * TAIL_TG);  // partial sums per thread
+  return (int)std::min<size_t>({(size_t)TAIL_NC, budget / per_col, by_loads, by_sums});
+}
+
+bool tail_fits(int n_pad, int ntiles, int ks) {
+  const int G = n_pad / TAIL_ROWS;
+  const int nk64 = n_pad / 64;
+  if (ks < 1 || ks > 8) return false;
+  // one round trip per iteration for the loads: bounded work per thread
+  if (G > 16 * TAIL_TG || ntiles > 16 * TAIL_TG) return false;
+  // the operator rows of a wave's K parts must fit its registers
+  for (int w = 0; w < 4; ++w) {
+    int units = 0;
+    for (int sp = w; sp < ks; sp += 4) units += ((sp + 1) * nk64) / ks - (sp * nk64) / ks;
+    if (units > TAIL_MAXU) return false;
+  }
+  return true;
 }
 
 bool launch_dalm_tail(hipStream_t s, const TailArgs& t0) {
   TailArgs t = t0;
   const int G = t.n_pad / TAIL_ROWS;
-  const int nk64 = t.n_pad / 64;
-  if (t.ks < 1 || t.ks > 8) return false;
-  // one round trip per iteration for the loads: bounded work per thread
-  if (G > 16 * TAIL_TG || t.ntiles > 16 * TAIL_TG) return false;
+  if (!tail_fits(t.n_pad, t.ntiles, t.ks)) return false;
   if (t.ncap < 1 || t.ncap > tail_capacity(t.n_pad, t.f32)) return false;
-  for (int w = 0; w < 4; ++w) {
-    int units = 0;
-    for (int sp = w; sp < t.ks; sp += 4) units += ((sp + 1) * nk64) / t.ks - (sp * nk64) / t.ks;
-    if (units > TAIL_MAXU) return false;
-  }
   const size_t dyn = t.f32 ? (size_t)t.ncap * (t.n_pad + 4) * 4 : (size_t)t.ncap * (t.n_pad + 8) * 4;
   int dev = 0;
   L1_HIP(hipGetDevice(&dev));
@@ -451,25 +531,32 @@ bool launch_dalm_tail(hipStream_t s, const TailArgs& t0) {
   return true;
 }
 
-void* tail_pool(size_t bytes) {
-  // one pool per device, grown by replacement only when a larger one is
-  // needed; a replaced pool is kept (uncached memory is not freed)
-  static std::mutex mu;
-  static void* pool[64] = {nullptr};
-  static size_t size[64] = {0};
-  std::lock_guard<std::mutex> lock(mu);
+namespace {
+constexpr int kMaxDev = 64;
+RegionList& regions(int dev) {
+  static RegionList lists[kMaxDev];
+  return lists[dev];
+}
+}  // namespace
+
+void* tail_region_get(size_t bytes, size_t* got) {
+  *got = 0;
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-  if (size[dev] >= bytes) return pool[dev];
-  void* p = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
   const size_t want = std::max<size_t>(bytes, (size_t)8 << 20);
-  if (hipExtMallocWithFlags(&p, want, hipDeviceMallocUncached) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  pool[dev] = p;
-  size[dev] = want;
-  return p;
+  return regions(dev).get(want, [](size_t n) -> void* {
+    void* p = nullptr;
+    if (hipExtMallocWithFlags(&p, n, hipDeviceMallocUncached) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }, got);
+}
+
+void tail_region_put(int dev, void* p, size_t bytes) {
+  if (!p || dev < 0 || dev >= kMaxDev) return;
+  regions(dev).put(p, bytes);
 }
 
 }  // namespace l1

@@ -12,6 +12,8 @@ import pytest
 from oracle import unrolled_vjp, unrolled_grad
 from workloads import cab_problem, tiny_dense
 
+from _parity import assert_cols_close, assert_all_close, rel_err_cols
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +49,8 @@ def test_cab_backward_matches_oracle(K, every):
     gb, gB = pl.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"),
                          torch.as_tensor(ge, dtype=torch.float32, device="cuda"))
     gb_o, gB_o = unrolled_vjp(P.A, P.b, _beta(P.b), K, gx, ge)
-    assert _rel(_np(gb), gb_o) < 1e-3
-    assert _rel(_np(gB), gB_o) < 1e-3
+    assert_cols_close(_np(gb), gb_o, 1e-3, what="_np(gb)")
+    assert_all_close(_np(gB), gB_o, 1e-3, what="_np(gB)")
 
 
 def test_dense_backward_equals_cab_on_the_same_matrix():
@@ -65,8 +67,8 @@ def test_dense_backward_equals_cab_on_the_same_matrix():
     gw = np.vstack([gx, ge])
     gb, gA = pl.backward(torch.as_tensor(gw, dtype=torch.float32, device="cuda"))
     gb_o, gB_o = unrolled_vjp(P.A, P.b, _beta(P.b), 15, gx, ge)
-    assert _rel(_np(gb), gb_o) < 1e-3
-    assert _rel(_np(gA)[:, :P.n_dict], gB_o) < 1e-3
+    assert_cols_close(_np(gb), gb_o, 1e-3, what="_np(gb)")
+    assert_all_close(_np(gA)[:, :P.n_dict], gB_o, 1e-3, what="_np(gA)[:, :P.n_dict]")
 
 
 def test_unrolled_function_loss_gradient():
@@ -77,7 +79,10 @@ def test_unrolled_function_loss_gradient():
     K = 50
     B = torch.as_tensor(P.A, device="cuda").requires_grad_(True)
     b = torch.as_tensor(P.b, device="cuda").requires_grad_(True)
-    x, e = DALMUnrolled.apply(b, B, K, 10)
+    # beta is an input of the map, held constant (here the default ||b||_1/m,
+    # computed by the caller and detached)
+    beta = torch.as_tensor(_beta(P.b), dtype=torch.float32, device="cuda")
+    x, e = DALMUnrolled.apply(b, B, beta, K, 10)
     C, pc = 20, 7
     Bd, bd, xd, ed = B.double(), b.double(), x.double(), e.double()
     res = torch.stack([torch.linalg.vector_norm(bd - ed - Bd[:, c * pc:(c + 1) * pc]
@@ -86,10 +91,24 @@ def test_unrolled_function_loss_gradient():
     lab = torch.as_tensor(P.labels, device="cuda")
     loss = torch.nn.functional.cross_entropy((-res).t(), lab)
     loss.backward()
-    l_o, gb_o, gB_o = unrolled_grad(P.A, P.b, _beta(P.b), K, P.labels, pc)
+    l_o, gb_o, gB_o = unrolled_grad(P.A, P.b, beta.cpu().numpy(), K, P.labels, pc)
     assert abs(loss.item() - l_o) < 1e-4 * abs(l_o)
-    assert _rel(_np(b.grad), gb_o) < 1e-3
-    assert _rel(_np(B.grad), gB_o) < 1e-3
+    assert_cols_close(_np(b.grad), gb_o, 1e-3, what="_np(b.grad)")
+    assert_all_close(_np(B.grad), gB_o, 1e-3, what="_np(B.grad)")
+
+
+def _kink_margin(B, b, beta, K):
+    """Per instance, the smallest distance of a clamp argument |s| to 1 over
+    the K iterations of the FP64 forward map (oracle arithmetic, Algorithm 2
+    written out here with the oracle's inverse): where it is below the FP32
+    rounding of s, the FP32 forward may take the other side of the kink and
+    its reverse pass the other derivative (0 instead of 1) there."""
+    from oracle.unrolled import unrolled_dalm
+    _, _, (tape, *_r) = unrolled_dalm(B, b, beta, K, keep_tape=True)
+    marg = np.full(b.shape[1], np.inf)
+    for t in tape:
+        marg = np.minimum(marg, np.min(np.abs(np.abs(t[2]) - 1.0), axis=0))
+    return marg
 
 
 def test_backward_full_size():
@@ -103,8 +122,17 @@ def test_backward_full_size():
     gb, gB = pl.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"),
                          torch.as_tensor(ge, dtype=torch.float32, device="cuda"))
     gb_o, gB_o = unrolled_vjp(P.A, P.b, _beta(P.b), 50, gx, ge)
-    assert _rel(_np(gb), gb_o) < 1e-3
-    assert _rel(_np(gB), gB_o) < 1e-3
+    err = rel_err_cols(_np(gb), gb_o)
+    marg = _kink_margin(P.A, P.b, _beta(P.b), 50)
+    near = marg < 1e-4
+    print(f"gb per-instance rel. l2: max {err.max():.2e}, median {np.median(err):.2e}, "
+          f"> 1e-3: {int((err > 1e-3).sum())}; instances with a clamp argument within 1e-4 of "
+          f"|s| = 1: {int(near.sum())}; their max {err[near].max() if near.any() else 0:.2e}, "
+          f"others' max {err[~near].max() if (~near).any() else 0:.2e}")
+    print("worst instances", np.argsort(-err)[:8].tolist(), "margins", marg[np.argsort(-err)[:8]].tolist())
+    print(f"gB rel. l2 {np.linalg.norm(_np(gB) - gB_o) / np.linalg.norm(gB_o):.2e}")
+    assert np.linalg.norm(_np(gb) - gb_o) / np.linalg.norm(gb_o) < 1e-3
+    assert np.linalg.norm(_np(gB) - gB_o) / np.linalg.norm(gB_o) < 1e-3
 
 
 def test_backward_without_tape_and_bad_plans():
@@ -124,3 +152,25 @@ def test_backward_without_tape_and_bad_plans():
                precision="bf16x3")
     with pytest.raises(L1Error):
         pl3.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-5)
+
+
+def test_explicit_penalty_is_the_map_input():
+    # a per-instance beta passed to the solve (not the default) is the one
+    # the forward map and its gradient use
+    P = cab_problem(m=130, classes=7, per_class=7, N=6, cfg=224)
+    from paper_1007_3753_amd import Plan
+    pl = Plan(torch.as_tensor(P.A, device="cuda"), structure="cab", max_batch=6,
+              record_tape=True, checkpoint_every=5)
+    beta = _beta(P.b) * np.array([0.5, 0.7, 1.0, 1.3, 2.0, 3.0])
+    b = torch.as_tensor(P.b, device="cuda")
+    r = pl.solve(b, max_iter=-17, want_y=False, pen=torch.as_tensor(beta, dtype=torch.float32))
+    from oracle import unrolled_dalm
+    xo, eo, _ = unrolled_dalm(P.A, P.b, beta.astype(np.float32).astype(np.float64), 17)
+    assert_cols_close(_np(r.x), xo, 5e-5, what="x")
+    assert_cols_close(_np(r.e), eo, 5e-5, what="e")
+    gx, ge = _adjoints(P.n_dict, P.m, 6, 17)
+    gb, gB = pl.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"),
+                         torch.as_tensor(ge, dtype=torch.float32, device="cuda"))
+    gb_o, gB_o = unrolled_vjp(P.A, P.b, beta.astype(np.float32).astype(np.float64), 17, gx, ge)
+    assert_cols_close(_np(gb), gb_o, 1e-3, what="gb")
+    assert_all_close(_np(gB), gB_o, 1e-3, what="gB")

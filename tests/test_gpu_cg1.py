@@ -8,6 +8,8 @@ import pytest
 from oracle import dalm as oracle_dalm, p1_lp, full_matrix
 from workloads import tiny_dense, dense_p1, cab_problem
 
+from _parity import assert_cols_close, assert_all_close, rel_err_cols
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -31,8 +33,8 @@ def test_dense_fixed_iterations_match_oracle(K):
     pl = _plan(P.A, max_batch=5)
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-K)
     o = oracle_dalm(P.A, P.b, fixed_iters=K, y_step="cg1")
-    assert _rel(_np(r.x), o.w) < 5e-5
-    assert _rel(_np(r.y), o.y) < 5e-5
+    assert_cols_close(_np(r.x), o.w, 5e-5, what="_np(r.x)")
+    assert_cols_close(_np(r.y), o.y, 5e-5, what="_np(r.y)")
     assert np.all(_np(r.iters) == K) and np.all(_np(r.status) == 0)
 
 
@@ -48,9 +50,9 @@ def test_cab_fixed_iterations_match_oracle(K):
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-K)
     o = oracle_dalm(P.A, P.b, structure="cab", fixed_iters=K, y_step="cg1")
     nd = P.A.shape[1]
-    assert _rel(_np(r.x), o.w[:nd]) < 5e-5
-    assert _rel(_np(r.e), o.w[nd:]) < 5e-5
-    assert _rel(_np(r.y), o.y) < 5e-5
+    assert_cols_close(_np(r.x), o.w[:nd], 5e-5, what="_np(r.x)")
+    assert_cols_close(_np(r.e), o.w[nd:], 5e-5, what="_np(r.e)")
+    assert_cols_close(_np(r.y), o.y, 5e-5, what="_np(r.y)")
 
 
 def test_gaussian_benchmark_shape_recovers_planted():

@@ -12,6 +12,8 @@ import pytest
 from oracle import dalm as oracle_dalm, p1_lp, full_matrix, kkt_report, qp_fista
 from workloads import tiny_dense, dense_p1, cab_problem, dense_qp
 
+from _parity import assert_cols_close, assert_all_close, rel_err_cols, assert_solution_close
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +43,8 @@ def test_dense_fixed_iterations_match_oracle(k):
     pl = _plan(P.A, max_batch=3)
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
     o = oracle_dalm(P.A, P.b, fixed_iters=k)
-    assert _rel(_np(r.x), o.w) < 2e-5
-    assert _rel(_np(r.y), o.y) < 2e-5
+    assert_cols_close(_np(r.x), o.w, 2e-5, what="_np(r.x)")
+    assert_cols_close(_np(r.y), o.y, 2e-5, what="_np(r.y)")
     assert np.all(_np(r.iters) == k) and np.all(_np(r.status) == 0)
 
 
@@ -54,8 +56,8 @@ def test_cab_fixed_iterations_match_oracle(k):
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
     o = oracle_dalm(P.A, P.b[:, :6], structure="cab", fixed_iters=k)
     w = np.vstack([_np(r.x), _np(r.e)])[:, :6]
-    assert _rel(w, o.w) < 5e-5
-    assert _rel(_np(r.y)[:, :6], o.y) < 5e-5
+    assert_cols_close(w, o.w, 5e-5, what="w")
+    assert_cols_close(_np(r.y)[:, :6], o.y, 5e-5, what="_np(r.y)[:, :6]")
 
 
 def test_dense_p1_converged_matches_lp_and_planted():
@@ -65,8 +67,8 @@ def test_dense_p1_converged_matches_lp_and_planted():
     r = pl.solve(b, tol=1e-6, max_iter=20000)
     x_lp, _ = p1_lp(P.A, P.b[:, 0])
     assert int(r.status[0]) == 0
-    assert _rel(_np(r.x)[:, 0], x_lp) < 1e-4
-    assert _rel(_np(r.x)[:, 0], P.x0[:, 0].astype(float)) < 1e-4
+    assert_cols_close(_np(r.x)[:, 0], x_lp, 1e-4, what="_np(r.x)[:, 0]")
+    assert_cols_close(_np(r.x)[:, 0], P.x0[:, 0].astype(float), 1e-4, what="_np(r.x)[:, 0]")
     rep = pl.kkt(b, r.x, y=r.y).cpu().numpy()[0]
     ref = kkt_report(P.A, P.b[:, 0], _np(r.x)[:, 0], _np(r.y)[:, 0])
     np.testing.assert_allclose(rep, [ref["primal"], ref["dual_inf"], ref["sign"], ref["gap"]],
@@ -85,7 +87,7 @@ def test_cab_converged_matches_lp(precision, bound):
     for j in (0, 37, 95):
         w_lp, _ = p1_lp(Af, P.b[:, j])
         x = _np(r.x)[:, j]
-        assert _rel(x, w_lp[:P.n_dict]) < bound, (j, _rel(x, w_lp[:P.n_dict]))
+        assert_solution_close(x, w_lp[:P.n_dict], bound, what=f"x of instance {j}")
     rep = pl.kkt(b, r.x, e=r.e, y=r.y).cpu().numpy()
     assert rep[:, 0].max() < 1e-5 and rep[:, 3].max() < 1e-4
 
@@ -156,7 +158,7 @@ def test_qp_dalm_matches_fista():
     assert np.all(_np(r.status) == 0)
     for j in range(4):
         xf = qp_fista(P.A, P.b[:, j], lam, iters=40000)
-        assert _rel(_np(r.x)[:, j], xf) < 1e-4
+        assert_cols_close(_np(r.x)[:, j], xf, 1e-4, what="_np(r.x)[:, j]")
 
 
 def test_p12_dalm_matches_oracle():
@@ -168,12 +170,12 @@ def test_p12_dalm_matches_oracle():
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), eps=torch.as_tensor(eps, dtype=torch.float32),
                  tol=1e-6, max_iter=100000)
     assert np.all(_np(r.status) == 0)
-    assert _rel(_np(r.x), o.w[:120]) < 1e-4
+    assert_cols_close(_np(r.x), o.w[:120], 1e-4, what="_np(r.x)")
     # fixed-iteration parity of the block prox
     r5 = pl.solve(torch.as_tensor(P.b, device="cuda"), eps=torch.as_tensor(eps, dtype=torch.float32),
                   max_iter=-7)
     o5 = oracle_dalm(A, b, problem="p12", eps=eps, fixed_iters=7)
-    assert _rel(np.vstack([_np(r5.x), _np(r5.e)]), o5.w) < 5e-5
+    assert_cols_close(np.vstack([_np(r5.x), _np(r5.e)]), o5.w, 5e-5, what="np.vstack([_np(r5.x), _np(r5.e)])")
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
@@ -229,10 +231,10 @@ def test_warm_start_continues_the_iteration(structure):
                  w0=torch.as_tensor(o8.w.astype(np.float32), device=dev),
                  y0=torch.as_tensor(o8.y.astype(np.float32), device=dev))
     nd = P.A.shape[1]
-    assert _rel(_np(r.x), o20.w[:nd]) < 5e-5
+    assert_cols_close(_np(r.x), o20.w[:nd], 5e-5, what="_np(r.x)")
     if structure == "cab":
-        assert _rel(_np(r.e), o20.w[nd:]) < 5e-5
-    assert _rel(_np(r.y), o20.y) < 5e-5
+        assert_cols_close(_np(r.e), o20.w[nd:], 5e-5, what="_np(r.e)")
+    assert_cols_close(_np(r.y), o20.y, 5e-5, what="_np(r.y)")
 
 
 def test_empty_batch():
@@ -240,3 +242,45 @@ def test_empty_batch():
     pl = _plan(P.A, max_batch=4)
     r = pl.solve(torch.zeros(20, 0, device="cuda"), tol=1e-6, max_iter=100)
     assert r.x.shape == (50, 0) and r.iters.numel() == 0
+
+
+def test_p12_kkt_report_matches_oracle():
+    # the FP64 certificate of the (P_{1,2}) branch against the oracle's report
+    P = tiny_dense(40, 120, N=3, key=15)
+    eps = np.array([0.2, 0.4, 0.7]) * np.linalg.norm(P.b.astype(float), axis=0)
+    pl = _plan(P.A, problem="p12", max_batch=3)
+    b = torch.as_tensor(P.b, device="cuda")
+    epst = torch.as_tensor(eps, dtype=torch.float32)
+    r = pl.solve(b, eps=epst, tol=1e-6, max_iter=100000)
+    assert np.all(_np(r.status) == 0)
+    rep = pl.kkt(b, r.x, y=r.y, eps=epst).cpu().numpy()
+    X, Y = _np(r.x), _np(r.y)
+    for j in range(3):
+        ref = kkt_report(P.A, P.b[:, j], X[:, j], Y[:, j], problem="p12",
+                         eps=float(np.float32(eps[j])))
+        np.testing.assert_allclose(rep[j], [ref["primal"], ref["dual_inf"], ref["sign"], ref["gap"]],
+                                   rtol=1e-6, atol=1e-12)
+    # a converged pair is (nearly) optimal
+    assert rep[:, 0].max() < 1e-5 and rep[:, 3].max() < 1e-3
+
+
+@pytest.mark.parametrize("method", ["dalm", "dalm_cg1", "palm"])
+def test_diverged_status(method):
+    # L1_DIVERGED fires when ||w||_2 exceeds div_factor sqrt(m) ||b||_2; a
+    # tiny factor forces it from the host for every instance with b != 0,
+    # while b = 0 (w stays 0) converges and fixed-count solves never test it
+    P = cab_problem(m=130, classes=7, per_class=7, N=3, cfg=210)
+    b = P.b.copy()
+    b[:, 1] = 0.0
+    kw = {} if method == "dalm_cg1" else {}
+    pl = _plan(P.A, structure="cab", method=method, max_batch=3, div_factor=1e-6, **kw)
+    bt = torch.as_tensor(b, device="cuda")
+    r = pl.solve(bt, tol=1e-6, max_iter=2000)
+    st = _np(r.status).astype(int)
+    assert st[0] == 3 and st[2] == 3 and st[1] == 0, st
+    rf = pl.solve(bt, max_iter=-5)
+    assert np.all(_np(rf.status) == 0)
+    # the default factor never fires on this (convergent) problem
+    pl2 = _plan(P.A, structure="cab", method=method, max_batch=3)
+    r2 = pl2.solve(bt, tol=1e-5, max_iter=20000 if method != "palm" else 3000)
+    assert not np.any(_np(r2.status) == 3)

@@ -14,6 +14,8 @@ import pytest
 
 from oracle import p1_lp, full_matrix, kkt_report
 from workloads import cab_problem, dense_qp
+from workloads.generators import cab_dictionary, cab_instances
+from _parity import assert_cols_close, rel_err_cols, assert_solution_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -46,10 +48,13 @@ def test_cab_1200x700_n512(precision, tol, bound):
     Af = full_matrix(P.A, "cab")
     for j in (0, 255, 511):
         w_lp, _ = p1_lp(Af, P.b[:, j])
-        assert _rel(X[:, j], w_lp[:P.n_dict]) < bound
-        assert _rel(np.concatenate([X[:, j], E[:, j]]), w_lp) < bound
-    # every instance: planted solution (exact recovery at 30 % corruption) and certificate
-    assert np.max(np.linalg.norm(X - P.x0, axis=0) / np.linalg.norm(P.x0, axis=0)) < 5 * bound
+        assert_solution_close(X[:, j], w_lp[:P.n_dict], bound, what=f"x of instance {j}")
+        assert_solution_close(np.concatenate([X[:, j], E[:, j]]), w_lp, bound, what=f"w of instance {j}")
+    # every instance within the promised bound of its planted solution (the
+    # exact l1 optimum at 30 % corruption: the LP reproduces the planted x0 to
+    # 1e-7 on the sampled instances above and in the benchmark's checks)
+    err = rel_err_cols(X, P.x0)
+    assert err.max() < bound, (int(err.argmax()), err.max())
     rep = pl.kkt(b, r.x, e=r.e, y=r.y).cpu().numpy()
     assert rep[:, 0].max() < 1e-5 and rep[:, 1].max() < 2e-3 and rep[:, 3].max() < 1e-4
     ref = kkt_report(Af, P.b[:, 7], np.concatenate([X[:, 7], E[:, 7]]), Y[:, 7])
@@ -57,26 +62,56 @@ def test_cab_1200x700_n512(precision, tol, bound):
                                rtol=1e-6, atol=1e-12)
 
 
+def _c4_golden():
+    path = os.path.join(GOLDEN, "c4_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c4_reference.npz not generated")
+    return np.load(path)
+
+
+def test_cab_4800x2100_golden_instances():
+    # the exact LP optima (oracle, certified to 1e-9) of 8 instances of the
+    # 4800 x 2100 workload -- the five most corrupted (~50 %), two at 35 %,
+    # one at 10 % -- solved in one batch, element by element at the bound
+    # BF16 + refinement promises; every instance must converge
+    g = _c4_golden()
+    idx = [int(j) for j in g["idx"]]
+    B = cab_dictionary(4800, 300, 7, cfg=4)
+    b = np.concatenate([cab_instances(B, 1, 7, frac="uneven", cfg=4, first=j)[0] for j in idx], axis=1)
+    pl = _plan(B, structure="cab", precision="bf16_refine", max_batch=len(idx))
+    r = pl.solve(torch.as_tensor(b, device="cuda"), tol=4e-6, max_iter=200000)
+    st = _np(r.status)
+    assert np.all(st == 0), (st, _np(r.iters))
+    X, E = _np(r.x), _np(r.e)
+    W = np.vstack([X, E])
+    assert_solution_close(X, g["w"][:2100], 1e-3, what="x")
+    assert_solution_close(W, g["w"], 1e-3, what="w")
+
+
 def test_cab_4800x2100_n2048():
-    # B 4800 x 2100, A = [B, I] (n = 6900), 2048 instances with corruption U[0, 0.5]
+    # B 4800 x 2100, A = [B, I] (n = 6900), 2048 instances with corruption
+    # U[0, 0.5], in the benchmark's launch configuration: every instance
+    # converges and sits within the bound of its planted solution (the LP
+    # optimum equals the planted x0 to 1e-7 on the golden instances, up to
+    # 50 % corruption); the golden instances element by element
     P = cab_problem(m=4800, classes=300, per_class=7, N=2048, frac="uneven", cfg=4)
     pl = _plan(P.A, structure="cab", precision="bf16_refine", max_batch=P.N)
     b = torch.as_tensor(P.b, device="cuda")
-    r = pl.solve(b, tol=4e-6, max_iter=40000)
+    r = pl.solve(b, tol=4e-6, max_iter=200000)
     st = _np(r.status)
-    assert np.all((st == 0) | (st == 1)) and np.mean(st == 0) > 0.7
+    assert np.all(st == 0), np.bincount(st.astype(int))
     X = _np(r.x)
-    err = np.linalg.norm(X - P.x0, axis=0) / np.linalg.norm(P.x0, axis=0)
-    p = (P.e0 != 0).sum(axis=0) / P.m
-    # up to 30 % corruption the planted solution is the l1 optimum (checked
-    # against the LP at 1200 x 700); the bound is the one BF16 + refinement promises
-    assert err[p <= 0.3].max() < 1e-3
+    err = rel_err_cols(X, P.x0)
+    assert err.max() < 1e-3, (int(err.argmax()), err.max())
+    g = _c4_golden()
+    for k, j in enumerate(g["idx"]):
+        assert_solution_close(X[:, j], g["w"][:2100, k], 1e-3, what=f"x of instance {j}")
     rep = pl.kkt(b, r.x, e=r.e, y=r.y).cpu().numpy()
     assert rep[:, 0].max() < 3e-5 and rep[:, 1].max() < 2e-3 and rep[:, 3].max() < 1e-3
 
 
 def test_qp_2000x8000_n64():
-    # Gaussian 2000 x 8000, +-1 spikes plus noise, lambda = 1e-3, 64 instances
+    # Gaussian 2000 x 8000, +-1 spikes plus noise, lambda = 1e-3, 64 instances, FP32
     P = dense_qp()
     beta = float(np.mean(np.abs(P.b.astype(np.float64)).sum(0) / P.m))
     pl = _plan(P.A, problem="qp", lam=P.lam, beta=beta, max_batch=P.N)
@@ -91,5 +126,6 @@ def test_qp_2000x8000_n64():
         ref = kkt_report(P.A, P.b[:, j], X[:, j], problem="qp", lam=P.lam)
         np.testing.assert_allclose(rep[j], [ref["primal"], ref["dual_inf"], ref["sign"], ref["gap"]],
                                    rtol=1e-6, atol=1e-12)
+    # the FP32 path promises 1e-4 against the FP64 optimum
     x_ref = np.load(os.path.join(GOLDEN, "qp_sweep_instance0.npy"))
-    assert _rel(X[:, 0], x_ref) < 1e-3
+    assert_solution_close(X[:, 0], x_ref, 1e-4, what="x of instance 0")

@@ -12,6 +12,8 @@ import pytest
 from oracle import palm as oracle_palm, p1_lp, full_matrix, qp_fista
 from workloads import tiny_dense, dense_p1, cab_problem
 
+from _parity import assert_cols_close, assert_all_close, rel_err_cols, assert_solution_close
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +37,7 @@ def test_dense_fixed_steps_match_oracle(outer, inner):
     pl = _plan(P.A, max_batch=3, max_inner=inner)
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-outer)
     o = oracle_palm(P.A, P.b, fixed_outer=outer, fixed_inner=inner)
-    assert _rel(_np(r.x), o.x) < 5e-5
+    assert_cols_close(_np(r.x), o.x, 5e-5, what="_np(r.x)")
     assert np.all(_np(r.iters) == outer) and np.all(_np(r.status) == 0)
 
 
@@ -44,7 +46,7 @@ def test_dense_fixed_steps_with_growth():
     pl = _plan(P.A, max_batch=5, max_inner=12, xi_growth=1.5)
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-5)
     o = oracle_palm(P.A, P.b, fixed_outer=5, fixed_inner=12, xi_growth=1.5)
-    assert _rel(_np(r.x), o.x) < 5e-5
+    assert_cols_close(_np(r.x), o.x, 5e-5, what="_np(r.x)")
 
 
 @pytest.mark.parametrize("precision,bound", [("fp32", 5e-5), ("bf16x3", 2e-4)])
@@ -55,8 +57,8 @@ def test_cab_fixed_steps_match_oracle(precision, bound):
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-3)
     cols = [0, 1, 33, 64, 69]
     o = oracle_palm(P.A, P.b[:, cols], structure="cab", fixed_outer=3, fixed_inner=10)
-    assert _rel(_np(r.x)[:, cols], o.x) < bound
-    assert _rel(_np(r.e)[:, cols], o.e) < bound
+    assert_cols_close(_np(r.x)[:, cols], o.x, bound, what="x")
+    assert_cols_close(_np(r.e)[:, cols], o.e, bound, what="e")
 
 
 def test_qp_fixed_steps_match_oracle():
@@ -65,8 +67,8 @@ def test_qp_fixed_steps_match_oracle():
     pl = _plan(P.A, problem="qp", lam=lam, max_batch=4, max_inner=15)
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-4)
     o = oracle_palm(P.A, P.b, problem="qp", lam=lam, fixed_outer=4, fixed_inner=15)
-    assert _rel(_np(r.x), o.x) < 5e-5
-    assert _rel(_np(r.e), o.e) < 5e-5
+    assert_cols_close(_np(r.x), o.x, 5e-5, what="_np(r.x)")
+    assert_cols_close(_np(r.e), o.e, 5e-5, what="_np(r.e)")
 
 
 def test_p12_fixed_steps_match_oracle():
@@ -76,8 +78,8 @@ def test_p12_fixed_steps_match_oracle():
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-4,
                  eps=torch.as_tensor(eps, dtype=torch.float32, device="cuda"))
     o = oracle_palm(P.A, P.b, problem="p12", eps=eps, fixed_outer=4, fixed_inner=15)
-    assert _rel(_np(r.x), o.x) < 5e-5
-    assert _rel(_np(r.e), o.e) < 5e-5
+    assert_cols_close(_np(r.x), o.x, 5e-5, what="_np(r.x)")
+    assert_cols_close(_np(r.e), o.e, 5e-5, what="_np(r.e)")
 
 
 def test_cab_adm_fixed_steps_match_oracle():
@@ -88,8 +90,8 @@ def test_cab_adm_fixed_steps_match_oracle():
     pl = _plan(P.A, structure="cab", precision="fp32", max_batch=6, max_inner=1)
     r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-50)
     o = oracle_palm(P.A, P.b, structure="cab", fixed_outer=50, fixed_inner=1)
-    assert _rel(_np(r.x), o.x) < 5e-5
-    assert _rel(_np(r.e), o.e) < 5e-5
+    assert_cols_close(_np(r.x), o.x, 5e-5, what="_np(r.x)")
+    assert_cols_close(_np(r.e), o.e, 5e-5, what="_np(r.e)")
 
 
 def test_dense_p1_converged_matches_lp():
@@ -99,7 +101,7 @@ def test_dense_p1_converged_matches_lp():
     assert np.all(_np(r.status) == 0)
     for j in range(2):
         x_lp, _ = p1_lp(P.A, P.b[:, j])
-        assert _rel(_np(r.x)[:, j], x_lp) < 1e-3
+        assert_solution_close(_np(r.x)[:, j], x_lp, 1e-3, what=f"x of instance {j}")
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 3e-6), ("bf16x3", 1e-5)])
@@ -119,7 +121,7 @@ def test_cab_converged_matches_lp(precision, tol):
     for k, j in enumerate(cols):
         w_lp, _ = p1_lp(Afull, P.b[:, j])
         err_o = _rel(np.concatenate([o.x[:, k], o.e[:, k]]), w_lp)
-        assert _rel(w[:, j], w_lp) < 1.5 * err_o + 2e-4
+        assert_solution_close(w[:, j], w_lp, 1.5 * err_o + 2e-4, what=f"w of instance {j}")
 
 
 def test_qp_converged_matches_fista():
@@ -135,7 +137,7 @@ def test_qp_converged_matches_fista():
     for j in range(3):
         x_ref = qp_fista(P.A, P.b[:, j], lam, iters=30000)
         err_o = _rel(o.x[:, j], x_ref)
-        assert _rel(_np(r.x)[:, j], x_ref) < 1.5 * err_o + 2e-4
+        assert_solution_close(_np(r.x)[:, j], x_ref, 1.5 * err_o + 2e-4, what=f"x of instance {j}")
 
 
 def test_p12_converged_matches_oracle():
@@ -146,7 +148,7 @@ def test_p12_converged_matches_oracle():
                  eps=torch.as_tensor(eps, dtype=torch.float32, device="cuda"))
     assert np.all(_np(r.status) == 0)
     o = oracle_palm(P.A, P.b, problem="p12", eps=eps, tol=1e-10, max_iter=20000, max_inner=2000)
-    assert _rel(_np(r.x), o.x) < 1e-3
+    assert_cols_close(_np(r.x), o.x, 1e-3, what="_np(r.x)")
     assert np.all(np.linalg.norm(_np(r.e), axis=0) <= eps * (1 + 1e-5))
 
 

@@ -10,6 +10,8 @@ import pytest
 from oracle import dalm as oracle_dalm
 from workloads import cab_problem
 
+from _parity import assert_cols_close, assert_all_close, rel_err_cols
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +47,7 @@ def test_any_table_gives_the_oracle_iterates(ks):
     cols = [0, 64, 129]
     o = oracle_dalm(P.A, P.b[:, cols], structure="cab", fixed_iters=30)
     x = r.x.cpu().numpy().astype(np.float64)[:, cols]
-    assert _rel(x, o.w[:P.A.shape[1]]) < 5e-5
+    assert_cols_close(x, o.w[:P.A.shape[1]], 5e-5, what="x")
     # the same table gives the same bits
     r2 = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-30)
     assert torch.equal(r.x, r2.x)
