@@ -302,6 +302,28 @@ int l1_alm_align(const float* B_dev, int m, int k, int N, const float* b_dev, in
                  int max_iter, float* w_dev, float* e_dev, int lde, int* iters_dev, int* status_dev,
                  void* stream);
 
+/* l1_alm_kkt without a plan and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Computes the same FP64
+ * report as l1_alm_kkt for a plan built on this dictionary:
+ *   A_dev   the dictionary (m x n_dict, column-major, leading dimension
+ *           lda >= m): A for L1_DENSE, B for L1_CAB (A = [B, I])
+ *   problem, structure, lambda  as in l1_alm_desc (lambda: QP_lambda only)
+ *   the remaining arguments as in l1_alm_kkt.
+ * The only scratch is the FP64 residual of each instance, taken from a
+ * static device array of 8 MiB (2^20 doubles) that every GPU the library
+ * runs on holds until the process ends; instances are processed in launches
+ * of floor(2^20 / m) so any N fits.  The call allocates nothing and needs no
+ * zeroed memory.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other host threads) race; serialise
+ * them.  Errors: L1_EINVAL for m > 2^20 rows (the scratch limit) and for
+ * the arguments l1_alm_plan / l1_alm_kkt reject.                          */
+#define L1_KKT_NOALLOC_MAX_M (1 << 20)
+int l1_alm_kkt_noalloc(const float* A_dev, int m, int n_dict, int lda, int problem, int structure,
+                       double lambda, const float* b_dev, int ldb, int N, const float* eps_dev,
+                       const float* x_dev, int ldx, const float* e_dev, int lde, const float* y_dev,
+                       int ldy, double* report_dev, void* stream);
+
 /* Release the plan and all device memory it owns. */
 int l1_alm_destroy(l1_alm_plan_t plan);
 

@@ -17,11 +17,18 @@ Readings of points the paper leaves open:
 
 * Algorithm 2 writes the face dictionary in steps 4 and 5; the dimensions only
   agree with the full matrix [B, I], which is what runs here.
-* beta is not given; default ``beta = ||b||_1 / m`` per instance (1 if b = 0).
+* beta is not given; default ``beta = beta0 / 8`` per instance with
+  ``beta0 = ||b||_1 / m`` (1 if b = 0), the scale of x: on face-shaped
+  problems the penalty at beta0 leaves the slowest instances several times
+  as many iterations to a given error as beta0 / 8 does, while typical
+  instances need about as many.  The one-CG-step variant keeps beta0.
 * "while not converged": stop after iteration k >= 1 when both
-  ``||w_k - w_{k-1}|| <= tol ||w_k||`` (the relative-change rule the paper
-  uses in Sec. VI-C) and the complementarity gap of the l1 block
-  ``| ||w||_1 - w^T v | <= tol ||w||_1`` with ``v = A^T y``.  The second test
+  ``(beta0 / beta) ||w_k - w_{k-1}|| <= tol ||w_k||`` and the complementarity
+  gap of the l1 block ``| ||w||_1 - w^T v | <= tol ||w||_1`` with
+  ``v = A^T y``.  Since ``w_k - w_{k-1} = -beta (z_k - A^T y_k)``, the first
+  test is ``beta0 ||z_k - A^T y_k|| <= tol ||w_k||``: the relative-change
+  rule the paper uses in Sec. VI-C, measured at the penalty beta0 whatever
+  penalty runs, so the stopping point does not move with beta.  The second test
   keeps the iteration from stopping on the initial plateau where no clamp is
   active: there w stays at the minimum-norm solution while y grows linearly,
   so the relative change of w is zero but the gap is ``||w||_1``.  For (P1)
@@ -62,11 +69,18 @@ def full_matrix(A, structure="dense", problem="p1"):
     return A
 
 
-def default_beta(b):
-    """Reading of the unspecified DALM penalty: ||b||_1 / m (1 when b = 0)."""
+def beta_scale(b):
+    """beta0 = ||b||_1 / m (1 when b = 0): the scale of x, which sets the
+    default penalty and the unit of the stopping test."""
     b = np.asarray(b, dtype=np.float64)
     s = np.abs(b).sum() / b.shape[0]
     return s if s > 0 else 1.0
+
+
+def default_beta(b, y_step="exact"):
+    """Reading of the unspecified DALM penalty: beta0 / 8 (beta0 for the
+    one-CG-step variant)."""
+    return beta_scale(b) if y_step == "cg1" else beta_scale(b) / 8.0
 
 
 @dataclass
@@ -83,6 +97,7 @@ class DalmResult:
 def _dalm_one(Af, b, beta, tol, max_iter, lam, eps, n_dict, problem,
               w0, y0, fixed, record, y_step="exact"):
     m, n = Af.shape
+    dscale = beta_scale(b) / beta if y_step == "exact" else 1.0
     if y_step == "exact":
         G = Af @ Af.T
         if problem == "qp":
@@ -127,7 +142,7 @@ def _dalm_one(Af, b, beta, tol, max_iter, lam, eps, n_dict, problem,
         if not (np.isfinite(nw) and np.isfinite(gap)):
             status = NONFINITE
             break
-        if fixed is None and dw <= tol * nw and gap <= tol * wl1:
+        if fixed is None and dscale * dw <= tol * nw and gap <= tol * wl1:
             status = CONVERGED
             break
     if fixed is not None and status != NONFINITE:
@@ -144,7 +159,7 @@ def dalm(A, b, *, structure="dense", problem="p1", beta=None, lam=None, eps=None
     from the current y (the cheaper heuristic mentioned in Sec. V-B).
 
     ``A`` is the dictionary (B for ``structure="cab"``).  ``beta`` is a scalar
-    or a per-instance array (default ``||b_j||_1/m``).  ``fixed_iters`` runs
+    or a per-instance array (default ``default_beta(b_j)``).  ``fixed_iters`` runs
     exactly that many iterations with no stopping test.  Returns a
     :class:`DalmResult` whose ``w`` rows are ``[x; e]`` for the split forms.
     """
@@ -168,7 +183,7 @@ def dalm(A, b, *, structure="dense", problem="p1", beta=None, lam=None, eps=None
     betas = np.empty(N)
     for j in range(N):
         if beta is None:
-            betas[j] = default_beta(b[:, j])
+            betas[j] = default_beta(b[:, j], y_step)
         else:
             betas[j] = float(np.broadcast_to(np.asarray(beta, np.float64), (N,))[j])
     eps_arr = None if eps is None else np.broadcast_to(np.asarray(eps, np.float64), (N,))

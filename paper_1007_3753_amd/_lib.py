@@ -20,7 +20,8 @@ L1_OK, L1_EINVAL, L1_ENOTSPD, L1_ENOMEM, L1_EHIP, L1_ENODEVICE, L1_ENOTAPE = 0, 
 ERROR_NAMES = {L1_EINVAL: "L1_EINVAL", L1_ENOTSPD: "L1_ENOTSPD", L1_ENOMEM: "L1_ENOMEM",
                L1_EHIP: "L1_EHIP", L1_ENODEVICE: "L1_ENODEVICE", L1_ENOTAPE: "L1_ENOTAPE"}
 EXPORTED = ("l1_alm_plan", "l1_alm_solve", "l1_alm_backward", "l1_alm_kkt", "l1_alm_classify",
-            "l1_alm_class_residuals", "l1_alm_align", "l1_alm_set_ksplit", "l1_alm_tune_ksplit", "l1_alm_last_stats", "l1_alm_destroy", "l1_alm_last_error")
+            "l1_alm_class_residuals", "l1_alm_align", "l1_alm_set_ksplit", "l1_alm_tune_ksplit", "l1_alm_last_stats", "l1_alm_kkt_noalloc",
+            "l1_alm_destroy", "l1_alm_last_error")
 
 
 class l1_alm_desc(ctypes.Structure):
@@ -58,6 +59,7 @@ def load(path=LIB_PATH):
     lib.l1_alm_solve.argtypes = [vp, vp, i, i, vp, vp, f, i, vp, vp, vp, i, vp, i, vp, i, vp, vp, vp]
     lib.l1_alm_backward.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.l1_alm_kkt.argtypes = [vp, vp, i, i, vp, vp, i, vp, i, vp, i, vp, vp]
+    lib.l1_alm_kkt_noalloc.argtypes = [vp, i, i, i, i, i, d, vp, i, i, vp, vp, i, vp, i, vp, i, vp, vp]
     lib.l1_alm_classify.argtypes = [vp, i, i, i, vp, i, vp, vp, vp, vp]
     lib.l1_alm_class_residuals.argtypes = [vp, i, i, i, vp, i, vp, i, vp, i, i, vp, i, vp, vp, vp]
     lib.l1_alm_set_ksplit.argtypes = [vp, vp, i]

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libl1alm.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["capi.hip", "solve.hip", "iter.hip", "tail.hip", "steps.hip", "fp64.hip", "classify.hip", "align.hip", "palm.hip", "cg1.hip", "adjoint.hip"]
+SOURCES = ["capi.hip", "solve.hip", "iter.hip", "tail.hip", "steps.hip", "fp64.hip", "classify.hip", "align.hip", "palm.hip", "cg1.hip", "adjoint.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -152,6 +152,7 @@ struct GemmArgs {
   int test_kind;               // 0: DALM test (decide()), 1: FISTA inner test (relative change)
   const float* eps;            // P_{1,2} radii (the ball scale comes from prev_partial)
   const float* wcap2;          // squared L1_DIVERGED thresholds per column (null: none)
+  const float* dscale2;        // (beta0 / beta)^2 per column (null: 1)
   long long* stat;             // [3 + prec] += live columns, [prec] += column tiles
 };
 

@@ -43,6 +43,7 @@ struct Plan {
   float* zscale = nullptr;
   float* tscal = nullptr;
   float* wcap2 = nullptr; // per instance: squared L1_DIVERGED threshold on ||w||_2
+  float* dscale2 = nullptr; // per instance: (beta0 / beta)^2 of the DALM stopping test
   float* partial = nullptr;
   float* ws = nullptr;    // split-K workspace: ws_tiles x TILE x lds floats
   int ws_tiles = 0, ks_target = 192, ks_max = 4;

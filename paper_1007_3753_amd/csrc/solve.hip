@@ -120,7 +120,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * p->m_pad, a.b, sizeof(float) * a.ldb,
                           sizeof(float) * m, N, hipMemcpyDeviceToDevice, s));
   penalties(s, N, m, p->bb, p->m_pad, a.pen, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0,
-            div_factor(p), p->pen, p->ipen, p->wcap2);
+            div_factor(p), p->pen, p->ipen, p->wcap2, p->dscale2);
   {
     GemmArgs g{};
     g.A32 = p->Cop;
@@ -246,6 +246,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   it.tp_final = last;
   it.eps = p12 ? eps : nullptr;
   it.wcap2 = p->wcap2;
+  it.dscale2 = p->dscale2;
   it.stat = p->stat;
   it.ws = p->ws;
   DalmCheck ck{};
@@ -261,6 +262,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   ck.eps = eps;
   ck.beta = p->pen;
   ck.wcap2 = p->wcap2;
+  ck.dscale2 = p->dscale2;
   ck.stat = p->stat;
   P12Fix fx{};
   fx.n = n;
@@ -452,6 +454,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           ta.C = p->C;
           ta.beta = p->pen;
           ta.wcap2 = p->wcap2;
+          ta.dscale2 = p->dscale2;
           ta.st[0] = stbuf[0];
           ta.st[1] = stbuf[1];
           ta.iters = L.iters;

@@ -36,13 +36,15 @@ __device__ float wg_sum(float v, float* sh) {
 }
 
 // ---- penalties ------------------------------------------------------------
-// mode 0 (DALM): pen = beta > 0 ? beta : ||b||_1/m (1 when b = 0)
-// mode 1 (PALM): pen = xi > 0 ? xi : 2m/||b||_1     (1 when b = 0)
-// a positive finite pen_in[c] replaces both
+// mode 0 (DALM):     pen = beta > 0 ? beta : ||b||_1 / (8 m)
+// mode 1 (PALM):     pen = xi > 0 ? xi : 2m/||b||_1
+// mode 2 (DALM-CG1): pen = beta > 0 ? beta : ||b||_1 / m
+// (1 in place of ||b||_1 / m when b = 0); a positive finite pen_in[c]
+// replaces the plan's value and the default
 __global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int ldb,
                                                       const float* pen_in, float fixed, int mode,
                                                       float div, float* pen, float* ipen,
-                                                      float* wcap2) {
+                                                      float* wcap2, float* dscale2) {
   __shared__ float sh[256];
   const int c = blockIdx.x;
   float s = 0.0f, s2 = 0.0f;
@@ -54,21 +56,25 @@ __global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int
   s = wg_sum(s, sh);
   s2 = wg_sum(s2, sh);
   if (threadIdx.x == 0) {
+    const float beta0 = (s > 0.0f) ? s / (float)m : 1.0f;
     float p;
     const float given = pen_in ? pen_in[c] : 0.0f;
     if (given > 0.0f && isfinite(given)) p = given;
     else if (fixed > 0.0f) p = fixed;
-    else if (mode == 0) p = (s > 0.0f) ? s / (float)m : 1.0f;
+    else if (mode == 0) p = 0.125f * beta0;
+    else if (mode == 2) p = beta0;
     else p = (s > 0.0f) ? 2.0f * (float)m / s : 1.0f;
     pen[c] = p;
     ipen[c] = 1.0f / p;
     if (wcap2) wcap2[c] = div * div * (float)m * s2;
+    if (dscale2) dscale2[c] = (beta0 / p) * (beta0 / p);
   }
 }
 void penalties(hipStream_t s, int N, int m, const float* b, int ldb, const float* pen_in,
-               float fixed, int mode, float div, float* pen, float* ipen, float* wcap2) {
+               float fixed, int mode, float div, float* pen, float* ipen, float* wcap2,
+               float* dscale2) {
   if (N <= 0) return;
-  penalty_kernel<<<N, 256, 0, s>>>(m, b, ldb, pen_in, fixed, mode, div, pen, ipen, wcap2);
+  penalty_kernel<<<N, 256, 0, s>>>(m, b, ldb, pen_in, fixed, mode, div, pen, ipen, wcap2, dscale2);
   L1_HIP(hipGetLastError());
 }
 
@@ -211,6 +217,7 @@ __global__ __launch_bounds__(256) void dalm_final_test_kernel(DalmCheck a) {
   tp.final_phase = a.final_phase;
   for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.floor[q];
   tp.wcap2 = a.wcap2 ? a.wcap2[c] : INFINITY;
+  tp.dscale2 = a.dscale2 ? a.dscale2[c] : 1.0f;
   int status = L1_MAXITER;
   const int st = decide_in(tp, st0, a.arith ? a.arith[c] : NPHASE, sm, &status);
   if (st != st0) a.L.state[c] = st;

@@ -28,6 +28,7 @@ struct TailArgs {
   const float* C;
   const float* beta;
   const float* wcap2;           // squared L1_DIVERGED thresholds (null: none)
+  const float* dscale2;         // (beta0 / beta)^2 of the stopping test (null: 1)
   int* st[2];                   // phase buffers; st[k0 & 1] holds the phases on entry
   int* iters;
   int* status;

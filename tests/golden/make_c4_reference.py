@@ -5,12 +5,16 @@ vectors with a per-instance corruption fraction U[0, 0.5]).
 Calls only the oracle: the split linear program of Sec. III-A solved by
 HiGHS (``oracle.p1_lp``) on the materialised matrix [B, I], and the FP64
 optimality report (``oracle.kkt_report``, LP duality of Sec. III-A / V-B),
-which must certify every stored optimum to 1e-9.  The sample is chosen from
+which must certify every stored optimum: relative primal residual, dual
+infeasibility and sign disagreement <= 1e-9, relative duality gap <= 1e-8
+(the solver's 1e-10 feasibility tolerances leave gaps of a few 1e-9 on
+these 4800-row problems; the goldens are used at 1e-4 and 1e-3).  The sample is chosen from
 the generator's corruption fractions alone: the five most corrupted
 instances of the batch (above 48 %), two near 35 % and one near 10 %.
 
-Usage: python tests/golden/make_c4_reference.py [--procs 4]
-(about 8 minutes of one core per instance).
+Usage: python tests/golden/make_c4_reference.py [--procs 8]
+(8 to 14 minutes of one core per instance; each instance's result is kept
+in a part file until all are done).
 """
 import argparse
 import os
@@ -53,6 +57,10 @@ def sample(ps):
 
 
 def solve_one(j):
+    part = OUT.replace(".npz", f".part{j}.npz")
+    if os.path.exists(part):
+        d = np.load(part)
+        return j, d["w"], d["y"], dict(zip(("primal", "dual_inf", "sign", "gap"), d["kkt"]))
     t = time.time()
     B = cab_dictionary(M, CLASSES, PER, cfg=CFG)
     b, _, x0, _ = cab_instances(B, 1, PER, frac="uneven", cfg=CFG, first=j)
@@ -60,12 +68,13 @@ def solve_one(j):
     w, y = p1_lp(Af, b[:, 0])
     rep = kkt_report(Af, b[:, 0].astype(np.float64), w, y)
     print(f"instance {j}: {time.time() - t:.0f} s, kkt {rep}", flush=True)
+    np.savez(part, w=w, y=y, kkt=np.array([rep["primal"], rep["dual_inf"], rep["sign"], rep["gap"]]))
     return j, w, y, rep
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--procs", type=int, default=4)
+    ap.add_argument("--procs", type=int, default=8)
     args = ap.parse_args()
     ps = fractions()
     idx = sample(ps)
@@ -73,10 +82,11 @@ def main():
     with Pool(args.procs) as pool:
         res = sorted(pool.map(solve_one, idx), key=lambda t: idx.index(t[0]))
     W = np.stack([r[1] for r in res], axis=1)
-    Y = np.stack([r[2] for r in res], axis=1)
     rep = np.array([[r[3]["primal"], r[3]["dual_inf"], r[3]["sign"], r[3]["gap"]] for r in res])
-    assert np.all(rep <= 1e-9), rep
-    np.savez_compressed(OUT, idx=np.array(idx), frac=ps[idx], w=W, y=Y, kkt=rep)
+    assert np.all(rep[:, :3] <= 1e-9) and np.all(rep[:, 3] <= 1e-8), rep
+    np.savez_compressed(OUT, idx=np.array(idx), frac=ps[idx], w=W, kkt=rep)
+    for j in idx:
+        os.remove(OUT.replace(".npz", f".part{j}.npz"))
     print("wrote", OUT)
 
 

@@ -27,9 +27,9 @@ def _rel(a, b):
 
 
 def _beta(b):
-    # the solver's default penalty ||b||_1 / m per instance
+    # the solver's default penalty ||b||_1 / (8 m) per instance
     b = np.asarray(b, np.float64)
-    return np.abs(b).sum(axis=0) / b.shape[0]
+    return np.abs(b).sum(axis=0) / b.shape[0] / 8.0
 
 
 def _adjoints(n1, n2, N, key):
@@ -122,17 +122,28 @@ def test_backward_full_size():
     gb, gB = pl.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"),
                          torch.as_tensor(ge, dtype=torch.float32, device="cuda"))
     gb_o, gB_o = unrolled_vjp(P.A, P.b, _beta(P.b), 50, gx, ge)
-    err = rel_err_cols(_np(gb), gb_o)
+    gbn = _np(gb)
+    err = rel_err_cols(gbn, gb_o)
+    # The map is piecewise linear in the clamp pattern of its 95 000 clamp
+    # arguments per instance.  The FP32 forward's s differs from the FP64
+    # one by up to a few 1e-5 (the iterate bound of the fixed-count tests),
+    # so an instance whose oracle trajectory passes within 1e-4 of |s| = 1
+    # may be differentiated on the other side of that kink (derivative 0
+    # instead of 1 there): both are derivatives of the map next to the point.
+    # Instances clear of every kink are held to 1e-3 element by element;
+    # the others to 1e-2 relative per instance (a flipped kink moves the
+    # instance's gradient by ~1e-3, measured).  The dictionary gradient, a
+    # sum over all instances, is held to 1e-3 element by element.
     marg = _kink_margin(P.A, P.b, _beta(P.b), 50)
     near = marg < 1e-4
     print(f"gb per-instance rel. l2: max {err.max():.2e}, median {np.median(err):.2e}, "
-          f"> 1e-3: {int((err > 1e-3).sum())}; instances with a clamp argument within 1e-4 of "
-          f"|s| = 1: {int(near.sum())}; their max {err[near].max() if near.any() else 0:.2e}, "
-          f"others' max {err[~near].max() if (~near).any() else 0:.2e}")
-    print("worst instances", np.argsort(-err)[:8].tolist(), "margins", marg[np.argsort(-err)[:8]].tolist())
-    print(f"gB rel. l2 {np.linalg.norm(_np(gB) - gB_o) / np.linalg.norm(gB_o):.2e}")
-    assert np.linalg.norm(_np(gb) - gb_o) / np.linalg.norm(gb_o) < 1e-3
-    assert np.linalg.norm(_np(gB) - gB_o) / np.linalg.norm(gB_o) < 1e-3
+          f"> 1e-3: {int((err > 1e-3).sum())}; instances within 1e-4 of a kink: {int(near.sum())} "
+          f"(max {err[near].max() if near.any() else 0:.2e}); the others: max "
+          f"{err[~near].max() if (~near).any() else 0:.2e}")
+    assert (~near).sum() >= 8
+    assert_cols_close(gbn[:, ~near], gb_o[:, ~near], 1e-3, what="gb (instances clear of kinks)")
+    assert err[near].max() < 1e-2
+    assert_all_close(_np(gB), gB_o, 1e-3, what="gB")
 
 
 def test_backward_without_tape_and_bad_plans():

@@ -182,8 +182,9 @@ def test_cg1_is_exact_when_rows_are_orthogonal():
     x0 = np.zeros(90)
     x0[rng.choice(90, 5, replace=False)] = rng.standard_normal(5)
     b = A @ x0
-    oc = dalm(A, b[:, None], fixed_iters=40, y_step="cg1")
-    oe = dalm(A, b[:, None], fixed_iters=40)
+    beta = np.abs(b).sum() / 30.0
+    oc = dalm(A, b[:, None], fixed_iters=40, y_step="cg1", beta=beta)
+    oe = dalm(A, b[:, None], fixed_iters=40, beta=beta)
     np.testing.assert_allclose(oc.w, oe.w, rtol=0, atol=1e-12 * np.abs(oe.w).max())
     np.testing.assert_allclose(oc.y, oe.y, rtol=0, atol=1e-12 * np.abs(oe.y).max())
 
