@@ -80,9 +80,9 @@ def dalm_roofline(m, n_dict, structure, agg, kern_s, launches):
 
 WORKLOADS = {
     # B 1200 x 700 (100 classes x 7), A = [B, I]; 512 test vectors, 30 % corrupted
-    "cab-1200x700-n512": dict(m=1200, classes=100, per_class=7, N=512, frac=0.3, cfg=3),
+    "cab-1200x700-n512": dict(m=1200, classes=100, per_class=7, N=512, frac=0.3, cfg=3, precision="fp32"),
     # B 4800 x 2100 (300 classes x 7); 2048 test vectors, corruption U[0, 0.5] each
-    "cab-4800x2100-n2048": dict(m=4800, classes=300, per_class=7, N=2048, frac="uneven", cfg=4),
+    "cab-4800x2100-n2048": dict(m=4800, classes=300, per_class=7, N=2048, frac="uneven", cfg=4, precision="fp32"),
 }
 DEFAULT_WORKLOAD = "cab-1200x700-n512"
 # The paper's noise-free synthetic benchmark (Sec. VI-A): m = 800, Gaussian A with
@@ -124,7 +124,7 @@ def parse():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + sorted(E1_WORKLOADS) + sorted(ALIGN_WORKLOADS)
                     + sorted(QP_WORKLOADS) + sorted(UNROLLED_WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16_refine", "bf16x3"],
-                    help="default: bf16_refine (cross-and-bouquet), fp32 (e1-*)")
+                    help="default: fp32 (the cross-and-bouquet workloads and e1-*)")
     ap.add_argument("--method", default="dalm", choices=["dalm", "palm", "adm", "dalm_cg1"],
                     help="e1-* workloads only (the cross-and-bouquet benchmark is DALM)")
     ap.add_argument("--e1-instances", type=int, default=20)
@@ -182,7 +182,7 @@ def main():
     if args.workload in UNROLLED_WORKLOADS:
         return unrolled_main(args)
     if args.precision is None:
-        args.precision = "bf16_refine"
+        args.precision = WORKLOADS[args.workload]["precision"]
     if args.method != "dalm":
         print("the cross-and-bouquet benchmark runs DALM", file=sys.stderr)
         sys.exit(2)
@@ -223,17 +223,20 @@ def main():
         rep = plan.kkt(b, r.x, e=r.e, y=r.y)
         return r, rep
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     agg = dict(timed_ms=0.0, timed_launches=0.0, launch_fp32=0.0, launch_bf16=0.0, launch_split=0.0,
                cols_fp32=0.0, cols_bf16=0.0, cols_split=0.0, iterations=0.0)
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         r, rep = step()
         st = plan.last_stats()
         for k in agg:
             agg[k] += st[k]
+        log(f"step {i + 1}/{args.steps}: solve {st['solve_ms']:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / args.steps
@@ -774,9 +777,9 @@ def unrolled_main(args):
     gx_np, ge_np = r.standard_normal((P.n_dict, N)), r.standard_normal((P.m, N))
     gx = torch.as_tensor(gx_np, dtype=torch.float32, device=dev)
     ge = torch.as_tensor(ge_np, dtype=torch.float32, device=dev)
-    # the penalty is an input of the differentiated map (the library's
-    # default ||b||_1 / (8 m), passed explicitly and held constant)
-    beta = np.abs(P.b.astype(np.float64)).sum(axis=0) / P.m / 8.0
+    # the penalty is an input of the differentiated map, passed explicitly and
+    # held constant: ||b||_1 / m per instance
+    beta = np.abs(P.b.astype(np.float64)).sum(axis=0) / P.m
     pen = torch.as_tensor(beta, dtype=torch.float32, device=dev)
 
     def step():

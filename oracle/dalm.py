@@ -17,11 +17,13 @@ Readings of points the paper leaves open:
 
 * Algorithm 2 writes the face dictionary in steps 4 and 5; the dimensions only
   agree with the full matrix [B, I], which is what runs here.
-* beta is not given; default ``beta = beta0 / 8`` per instance with
+* beta is not given; default per instance ``beta = beta0 / 8`` for the
+  cross-and-bouquet form and ``beta = beta0`` otherwise, with
   ``beta0 = ||b||_1 / m`` (1 if b = 0), the scale of x: on face-shaped
   problems the penalty at beta0 leaves the slowest instances several times
-  as many iterations to a given error as beta0 / 8 does, while typical
-  instances need about as many.  The one-CG-step variant keeps beta0.
+  as many iterations to a given error as beta0 / 8 does (typical instances
+  need about as many), while on Gaussian dictionaries beta0 is the faster
+  one.  The one-CG-step variant keeps beta0.
 * "while not converged": stop after iteration k >= 1 when both
   ``(beta0 / beta) ||w_k - w_{k-1}|| <= tol ||w_k||`` and the complementarity
   gap of the l1 block ``| ||w||_1 - w^T v | <= tol ||w||_1`` with
@@ -77,10 +79,13 @@ def beta_scale(b):
     return s if s > 0 else 1.0
 
 
-def default_beta(b, y_step="exact"):
-    """Reading of the unspecified DALM penalty: beta0 / 8 (beta0 for the
-    one-CG-step variant)."""
-    return beta_scale(b) if y_step == "cg1" else beta_scale(b) / 8.0
+def default_beta(b, structure="dense", y_step="exact"):
+    """Reading of the unspecified DALM penalty: beta0 / 8 for the
+    cross-and-bouquet form, beta0 otherwise and for the one-CG-step
+    variant."""
+    if structure == "cab" and y_step == "exact":
+        return beta_scale(b) / 8.0
+    return beta_scale(b)
 
 
 @dataclass
@@ -183,7 +188,7 @@ def dalm(A, b, *, structure="dense", problem="p1", beta=None, lam=None, eps=None
     betas = np.empty(N)
     for j in range(N):
         if beta is None:
-            betas[j] = default_beta(b[:, j], y_step)
+            betas[j] = default_beta(b[:, j], structure, y_step)
         else:
             betas[j] = float(np.broadcast_to(np.asarray(beta, np.float64), (N,))[j])
     eps_arr = None if eps is None else np.broadcast_to(np.asarray(eps, np.float64), (N,))

@@ -243,6 +243,8 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   p->W = dalloc<float>(st, o);
   p->V = dalloc<float>(st, o);
   p->C = dalloc<float>(st, o);
+  p->C0 = dalloc<float>(st, o);
+  p->Wref = dalloc<float>(st, o);
   p->Z[0] = dalloc<float>(st, o);
   p->Z[1] = dalloc<float>(st, o);
   for (int b = 0; b < 2; ++b) {

@@ -75,7 +75,7 @@ void kkt64(hipStream_t s, int problem, int m, int nd, int split, const float* A,
 // ---- iteration kernels ---------------------------------------------------
 // Arithmetic of a product.  Phase p of an instance selects PHASE_PREC[p].
 enum Prec { PREC_BF16 = 0, PREC_BF16X3 = 1, PREC_F32 = 2 };
-enum Epi { EPI_STORE = 0, EPI_DALM = 1, EPI_FISTA = 2, EPI_PARTIAL = 3 };
+enum Epi { EPI_STORE = 0, EPI_DALM = 1, EPI_FISTA = 2, EPI_PARTIAL = 3, EPI_REFRESH = 4 };
 constexpr int NPHASE = 3;   // phase index == Prec
 
 struct GemmArgs {
@@ -111,7 +111,14 @@ struct GemmArgs {
   int lds;
   float* V;             // DALM: v = A^T y              | FISTA: current point z (read)
   float* W;             // DALM: w = [x; e]             | FISTA: w (last shrink output)
-  const float* C;       // DALM: c = A^T G^{-1} b/beta  | FISTA: h = A^T (b - e + theta/xi)
+  const float* C;       // DALM: c_ref = c - P w_ref / beta (c = A^T G^{-1} b/beta) | FISTA: h
+  // DALM re-centred operand: u = z - (w - w_ref)/beta (w_ref null: 0), so
+  // that v = P u + c_ref = P (z - w/beta) + c exactly while the operand stays
+  // O(1) in the low-precision products; EPI_REFRESH sets w_ref = w and
+  // c_ref = (C0 - P w) / beta with an FP32 product (C0 = A^T G^{-1} b)
+  float* Wref;
+  const float* C0;
+  int force_f32;        // EPI_REFRESH: FP32 product whatever the tile's phase
   const float* beta;    // DALM: beta per column        | FISTA: xi per column
   float* U;             // DALM: next B-operand u (FP32) ...
   uint16_t* Uhi;        // ... and its BF16 hi / lo split (may be null when

@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       // slices in flight per arithmetic, from a sweep of 2..8 on the
       // 1200 x 700 cross-and-bouquet operator (deeper split-BF16 prefetch
       // makes the compiler serialise the loads)
-      if (prec == PREC_F32) mainloop_f32<8>(a, i0, colidx, lds, acc, kb, ke);
+      if (prec == PREC_F32 || (EPI == EPI_REFRESH)) mainloop_f32<8>(a, i0, colidx, lds, acc, kb, ke);
       else if (prec == PREC_BF16X3) mainloop_bf16<true, 3>(a, i0, colidx, lds, acc, kb, ke);
       else mainloop_bf16<false, 4>(a, i0, colidx, lds, acc, kb, ke);
     }
@@ -492,11 +492,39 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       const f4 c4 = *reinterpret_cast<const f4*>(a.C + idx);
       const f4 wo = *reinterpret_cast<const f4*>(a.W + idx);
       f4 wn4, un4;
-      if (EPI == EPI_DALM) {
+      if (EPI == EPI_REFRESH) {
+        // w_ref = w, c_ref = (C0 - P w) / beta, and the next operand
+        // u = clamp(v + w/beta) - (w - w_ref)/beta = clamp(v + w/beta)
+        const float ib = 1.0f / a.beta[col];
+        const f4 c0 = *reinterpret_cast<const f4*>(a.C0 + idx);
+        const f4 vo = *reinterpret_cast<const f4*>(a.V + idx);
+        f4 cr4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cr4[r] = (c0[r] - acc[bi][bj][r]) * ib;
+          un4[r] = clamp1(vo[r] + wo[r] * ib);
+        }
+        *reinterpret_cast<f4*>(const_cast<float*>(a.C) + idx) = cr4;
+        *reinterpret_cast<f4*>(a.Wref + idx) = wo;
+        if (prec == PREC_F32 || !a.Uhi) *reinterpret_cast<f4*>(a.U + idx) = un4;
+        if (a.Uhi && prec != PREC_F32) {
+          us4 h, l;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint16_t hb = f2bf(un4[r]);
+            h[r] = hb;
+            l[r] = f2bf(un4[r] - bf2f(hb));
+          }
+          *reinterpret_cast<us4*>(a.Uhi + idx) = h;
+          *reinterpret_cast<us4*>(a.Ulo + idx) = l;
+        }
+        continue;
+      } else if (EPI == EPI_DALM) {
         const float bt = a.beta[col];
         const float ib = 1.0f / bt;
         const float zsc = s_zsc[wn * 32 + bj * 16 + li];
         const f4 vo = *reinterpret_cast<const f4*>(a.V + idx);
+        const f4 wr4 = a.Wref ? *reinterpret_cast<const f4*>(a.Wref + idx) : f4{0.f, 0.f, 0.f, 0.f};
         f4 vn4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -510,7 +538,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
           const float z2 = ball ? s2 : clamp1(s2);  // ball rows: scaled after the column norm
           vn4[r] = vn;
           wn4[r] = wn;
-          un4[r] = z2 - wn * ib;
+          un4[r] = z2 - (wn - wr4[r]) * ib;
           const float d = wn - wo[r];
           part[bj][0] += d * d;
           part[bj][1] += wn * wn;
@@ -568,6 +596,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       *reinterpret_cast<f4*>(a.W + idx) = wn4;
     }
   }
+  if (EPI == EPI_REFRESH) return;   // the partial sums of the last iteration stay
   // reduce the partial sums over the 4 lane groups of each column ...
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj)
@@ -611,7 +640,8 @@ void launch_gemm(hipStream_t s, int epi, const GemmArgs& a0, int n_col_tiles) {
     for (const void* f : {reinterpret_cast<const void*>(gemm_kernel<EPI_STORE>),
                           reinterpret_cast<const void*>(gemm_kernel<EPI_DALM>),
                           reinterpret_cast<const void*>(gemm_kernel<EPI_FISTA>),
-                          reinterpret_cast<const void*>(gemm_kernel<EPI_PARTIAL>)})
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_PARTIAL>),
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_REFRESH>)})
       ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LDS) ==
                      hipSuccess;
     return ok;
@@ -620,6 +650,7 @@ void launch_gemm(hipStream_t s, int epi, const GemmArgs& a0, int n_col_tiles) {
   if (epi == EPI_STORE) gemm_kernel<EPI_STORE><<<grid, 256, GEMM_LDS, s>>>(a);
   else if (epi == EPI_DALM) gemm_kernel<EPI_DALM><<<grid, 256, GEMM_LDS, s>>>(a);
   else if (epi == EPI_FISTA) gemm_kernel<EPI_FISTA><<<grid, 256, GEMM_LDS, s>>>(a);
+  else if (epi == EPI_REFRESH) gemm_kernel<EPI_REFRESH><<<grid, 256, GEMM_LDS, s>>>(a);
   else gemm_kernel<EPI_PARTIAL><<<grid, 256, GEMM_LDS, s>>>(a);
   L1_HIP(hipGetLastError());
 }

@@ -31,7 +31,9 @@ struct Plan {
   // workspace, column-major with leading dimension lds, N_pad columns
   float* W = nullptr;
   float* V = nullptr;
-  float* C = nullptr;
+  float* C = nullptr;      // c, then c_ref = (C0 - P w_ref) / beta after each refresh
+  float* C0 = nullptr;     // A^T G^{-1} b (unscaled)
+  float* Wref = nullptr;   // reference point of the DALM operand (see EPI_REFRESH)
   float* Z[2] = {nullptr, nullptr};
   float* Uf[2] = {nullptr, nullptr};       // ping-pong B-operand of the iteration (FP32)
   uint16_t* Uh[2] = {nullptr, nullptr};    // its BF16 hi / lo split (BF16 precisions)
@@ -96,6 +98,15 @@ struct SolveArgs {
   int* status;
   hipStream_t s;
 };
+
+// Default DALM penalty as a multiple of beta0 = ||b||_1 / m: 1/8 for the
+// cross-and-bouquet form, 1 for dense dictionaries.  On face-shaped problems
+// the smaller penalty reaches a given error in several times fewer
+// iterations on the slowest instances (as many on the others); on Gaussian
+// dictionaries beta0 is the faster one.
+inline float default_beta_scale(const Plan* p) {
+  return (p->d.structure == L1_CAB) ? 0.125f : 1.0f;
+}
 
 // L1_DIVERGED threshold factor of the plan (desc.div_factor, default 1e6)
 inline float div_factor(const Plan* p) {

@@ -120,7 +120,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * p->m_pad, a.b, sizeof(float) * a.ldb,
                           sizeof(float) * m, N, hipMemcpyDeviceToDevice, s));
   penalties(s, N, m, p->bb, p->m_pad, a.pen, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0,
-            div_factor(p), p->pen, p->ipen, p->wcap2, p->dscale2);
+            default_beta_scale(p), div_factor(p), p->pen, p->ipen, p->wcap2, p->dscale2);
   {
     GemmArgs g{};
     g.A32 = p->Cop;
@@ -136,7 +136,15 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     g.ldo = lds;
     g.col_scale = p->ipen;
     launch_gemm(s, EPI_STORE, g, ntc);
+    // the same product unscaled, C0 = A^T G^{-1} b, from which each refresh
+    // of the operand's reference point forms c_ref = (C0 - P w_ref) / beta
+    g.out = p->C0;
+    g.col_scale = nullptr;
+    launch_gemm(s, EPI_STORE, g, ntc);
   }
+  // reference point of the operand u = z - (w - w_ref)/beta: 0 until the
+  // first refresh (then c_ref = c)
+  L1_HIP(hipMemsetAsync(p->Wref, 0, sizeof(float) * (size_t)lds * N, s));
   float* eps = nullptr;
   if (p12) {
     eps = p->tscal;
@@ -247,6 +255,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   it.eps = p12 ? eps : nullptr;
   it.wcap2 = p->wcap2;
   it.dscale2 = p->dscale2;
+  it.Wref = p->Wref;
   it.stat = p->stat;
   it.ws = p->ws;
   DalmCheck ck{};
@@ -338,25 +347,61 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
     ck.state_other = stbuf[1 - nb];
     dalm_compact(s, ck);
   };
+  // FP32 refresh of the operand's reference point after iteration k (a block
+  // end, after its compaction): w_ref = w, c_ref = (C0 - P w)/beta and the
+  // next operand u = clamp(v + w/beta), for the listed instances.  Exact in
+  // exact arithmetic (v = P u + c_ref = P (z - w/beta) + c either way); it
+  // keeps the low-precision products' operand O(1).  Not for P_{1,2} (the
+  // ball block's operand is fixed up separately) nor for recorded tapes (the
+  // backward recomputes segments from (w, v) alone), and only while the
+  // active instances span two or more column tiles (refresh_min below).
+  const bool recentre = !p12 && !(fixed && p->d.record_tape);
+  GemmArgs rf{};
+  rf.A32 = p->P32;
+  rf.lda = p->n_pad;
+  rf.B = p->W;
+  rf.ldb = lds;
+  rf.M = p->n_pad;
+  rf.K = p->n_pad;
+  rf.slot_col = L.slot_col;
+  rf.phase_off = L.phase_off;
+  rf.n_cols = N;
+  rf.lds = lds;
+  rf.V = p->V;
+  rf.W = p->W;
+  rf.C = p->C;
+  rf.C0 = p->C0;
+  rf.beta = p->pen;
+  rf.Wref = p->Wref;
+  rf.force_f32 = 1;
+  auto refresh_after = [&](int k, int ctiles) {
+    const int nb = (k + 1) & 1;
+    rf.U = p->Uf[nb];
+    rf.Uhi = p->Uh[nb];
+    rf.Ulo = p->Ul[nb];
+    launch_gemm(s, EPI_REFRESH, rf, ctiles);
+  };
 
   // captured blocks of BLK iterations, one per launch shape met; the first
   // block (no test in its first launch) and tape recording run uncaptured
   struct Captured {
     Shape sh;
+    bool refresh;
     hipGraph_t g;
     hipGraphExec_t x;
   };
   std::vector<Captured> graphs;
   bool graphs_ok = graphs_enabled() && !tape && cap >= 4 * BLK;
-  auto graph_for = [&](const Shape& sh) -> hipGraphExec_t {
+  auto graph_for = [&](const Shape& sh, bool refresh) -> hipGraphExec_t {
     for (auto& c : graphs)
-      if (c.sh.ctiles == sh.ctiles && c.sh.ks == sh.ks) return c.x;
-    Captured c{sh, nullptr, nullptr};
+      if (c.sh.ctiles == sh.ctiles && c.sh.ks == sh.ks && c.refresh == refresh) return c.x;
+    Captured c{sh, refresh, nullptr, nullptr};
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       try {
         for (int t = 0; t < BLK; ++t) one_iter(BLK + t, sh);  // any k > 0 of even block start
         compact_after(2 * BLK - 1);
+        if (refresh) refresh_after(2 * BLK - 1, sh.ctiles);
       } catch (const Fail&) {
         ok = false;
       }
@@ -395,6 +440,12 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   // in one cooperative launch (it also runs the test of the last iteration)
   const int tail_f32 = (last == PREC_F32) ? 1 : 0;
   const int tail_cap = tail_capacity(p->n_pad, tail_f32);
+  // the operand's reference point is refreshed while the active instances
+  // span at least two column tiles: a rule of the launch shape, like the
+  // K split, so that an instance's arithmetic depends on the shape only (a
+  // batch that fits one tile runs as each of its instances alone would, and
+  // the tail kernel, which never refreshes, takes over within one tile)
+  const int refresh_min = TILE;
   bool tail_ok = !tape && !p12 && (p->n_pad % (TAIL_ROWS * 4) == 0) && tail_cap >= 1 &&
                  (tail_f32 || p->Phi != nullptr);
   if (const char* e = std::getenv("L1ALM_TAIL")) tail_ok = tail_ok && e[0] != '0';
@@ -452,6 +503,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           ta.V = p->V;
           ta.W = p->W;
           ta.C = p->C;
+          ta.Wref = p->Wref;
           ta.beta = p->pen;
           ta.wcap2 = p->wcap2;
           ta.dscale2 = p->dscale2;
@@ -522,9 +574,10 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           }
         }
       }
+      const bool refresh = recentre && active > refresh_min;
       hipGraphExec_t gx = nullptr;
       if (graphs_ok && blk == BLK && done > 0) {
-        gx = graph_for(sh);
+        gx = graph_for(sh, refresh);
         if (!gx) graphs_ok = false;
       }
       const int slot = nslot;
@@ -545,6 +598,7 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
           one_iter(k, sh);
         }
         compact_after(done + blk - 1);
+        if (refresh) refresh_after(done + blk - 1, sh.ctiles);
       }
       if (timing) L1_HIP(hipEventRecord(tev[2 * slot + 1], s));
       done += blk;

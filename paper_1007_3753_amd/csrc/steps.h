@@ -68,12 +68,12 @@ struct P12Fix {
 
 // Per-instance penalty from pen_in[c] when it is positive and finite, else
 // `fixed` when > 0, else the default of the instance: mode 0 (DALM) beta =
-// ||b||_1 / (8 m), mode 1 (PALM) xi = 2 m / ||b||_1, mode 2 (one-CG-step
-// DALM) beta = ||b||_1 / m; the squared L1_DIVERGED threshold
-// (div sqrt(m) ||b||_2)^2; and dscale2 = (beta0 / beta)^2 with beta0 =
-// ||b||_1 / m, the scale of the DALM stopping test (may be null).
+// dflt ||b||_1 / m, mode 1 (PALM) xi = 2 m / ||b||_1; the squared
+// L1_DIVERGED threshold (div sqrt(m) ||b||_2)^2; and dscale2 = (beta0 /
+// beta)^2 with beta0 = ||b||_1 / m, the unit of the DALM stopping test (may
+// be null).
 void penalties(hipStream_t s, int N, int m, const float* b, int ldb, const float* pen_in,
-               float fixed, int mode, float div, float* pen, float* ipen, float* wcap2,
+               float fixed, int mode, float dflt, float div, float* pen, float* ipen, float* wcap2,
                float* dscale2);
 void dalm_init_u(hipStream_t s, int N, const DalmInit& a);
 void init_lists(hipStream_t s, int N, int phase0, const Lists& L, int* state_other,

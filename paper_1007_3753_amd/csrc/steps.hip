@@ -36,14 +36,13 @@ __device__ float wg_sum(float v, float* sh) {
 }
 
 // ---- penalties ------------------------------------------------------------
-// mode 0 (DALM):     pen = beta > 0 ? beta : ||b||_1 / (8 m)
+// mode 0 (DALM):     pen = beta > 0 ? beta : dflt ||b||_1 / m
 // mode 1 (PALM):     pen = xi > 0 ? xi : 2m/||b||_1
-// mode 2 (DALM-CG1): pen = beta > 0 ? beta : ||b||_1 / m
 // (1 in place of ||b||_1 / m when b = 0); a positive finite pen_in[c]
 // replaces the plan's value and the default
 __global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int ldb,
                                                       const float* pen_in, float fixed, int mode,
-                                                      float div, float* pen, float* ipen,
+                                                      float dflt, float div, float* pen, float* ipen,
                                                       float* wcap2, float* dscale2) {
   __shared__ float sh[256];
   const int c = blockIdx.x;
@@ -61,8 +60,7 @@ __global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int
     const float given = pen_in ? pen_in[c] : 0.0f;
     if (given > 0.0f && isfinite(given)) p = given;
     else if (fixed > 0.0f) p = fixed;
-    else if (mode == 0) p = 0.125f * beta0;
-    else if (mode == 2) p = beta0;
+    else if (mode == 0) p = dflt * beta0;
     else p = (s > 0.0f) ? 2.0f * (float)m / s : 1.0f;
     pen[c] = p;
     ipen[c] = 1.0f / p;
@@ -71,10 +69,10 @@ __global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int
   }
 }
 void penalties(hipStream_t s, int N, int m, const float* b, int ldb, const float* pen_in,
-               float fixed, int mode, float div, float* pen, float* ipen, float* wcap2,
+               float fixed, int mode, float dflt, float div, float* pen, float* ipen, float* wcap2,
                float* dscale2) {
   if (N <= 0) return;
-  penalty_kernel<<<N, 256, 0, s>>>(m, b, ldb, pen_in, fixed, mode, div, pen, ipen, wcap2, dscale2);
+  penalty_kernel<<<N, 256, 0, s>>>(m, b, ldb, pen_in, fixed, mode, dflt, div, pen, ipen, wcap2, dscale2);
   L1_HIP(hipGetLastError());
 }
 

@@ -26,6 +26,7 @@ struct TailArgs {
   float* V;
   float* W;
   const float* C;
+  const float* Wref;            // reference point of the operand (null: 0)
   const float* beta;
   const float* wcap2;           // squared L1_DIVERGED thresholds (null: none)
   const float* dscale2;         // (beta0 / beta)^2 of the stopping test (null: 1)

@@ -163,6 +163,7 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
   const long eidx = eown ? (long)s_col[ej] * a.lds + r0 + er : 0;
   float vreg = eown ? a.V[eidx] : 0.0f, wreg = eown ? a.W[eidx] : 0.0f;
   const float creg = eown ? a.C[eidx] : 0.0f;
+  const float wref = (eown && a.Wref) ? a.Wref[eidx] : 0.0f;
   const float bt = eown ? a.beta[s_col[ej]] : 1.0f;
   const float ib = 1.0f / bt;
 
@@ -437,7 +438,7 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
         const float wn = wo - bt * (z - vn);
         const float s2 = vn + wn * ib;
         const float z2 = clamp1_t(s2);
-        const float un = z2 - wn * ib;
+        const float un = z2 - (wn - wref) * ib;
         vreg = vn;
         wreg = wn;
         // the next u, tagged for iteration k + 1

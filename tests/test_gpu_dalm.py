@@ -48,16 +48,21 @@ def test_dense_fixed_iterations_match_oracle(k):
     assert np.all(_np(r.iters) == k) and np.all(_np(r.status) == 0)
 
 
-@pytest.mark.parametrize("k", [1, 5, 60])
-def test_cab_fixed_iterations_match_oracle(k):
-    # 130 rows / 49 columns: several tiles with ragged edges in both dimensions
+@pytest.mark.parametrize("k,r", [(1, 5e-5), (5, 5e-5), (60, 2e-4)])
+def test_cab_fixed_iterations_match_oracle(k, r):
+    # 130 rows / 49 columns: several tiles with ragged edges in both dimensions.
+    # Per-element bound r (x column rms): FP32 products (unit 6e-8) over
+    # ~200-term sums, growing with the iterations; with the face-shaped
+    # default penalty beta0/8 the operand before the first refresh is
+    # O(||w||/beta), eight times that of beta0, whose rounding the later
+    # iterations carry (2e-4 at 60 iterations)
     P = cab_problem(m=130, classes=7, per_class=7, N=70, cfg=201)
     pl = _plan(P.A, structure="cab", max_batch=70)
-    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
+    r_ = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
     o = oracle_dalm(P.A, P.b[:, :6], structure="cab", fixed_iters=k)
-    w = np.vstack([_np(r.x), _np(r.e)])[:, :6]
-    assert_cols_close(w, o.w, 5e-5, what="w")
-    assert_cols_close(_np(r.y)[:, :6], o.y, 5e-5, what="_np(r.y)[:, :6]")
+    w = np.vstack([_np(r_.x), _np(r_.e)])[:, :6]
+    assert_cols_close(w, o.w, r, what="w")
+    assert_cols_close(_np(r_.y)[:, :6], o.y, r, what="y")
 
 
 def test_dense_p1_converged_matches_lp_and_planted():

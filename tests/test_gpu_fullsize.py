@@ -70,42 +70,47 @@ def _c4_golden():
 
 
 def test_cab_4800x2100_golden_instances():
-    # the exact LP optima (oracle, certified to 1e-9) of 8 instances of the
-    # 4800 x 2100 workload -- the five most corrupted (~50 %), two at 35 %,
-    # one at 10 % -- solved in one batch, element by element at the bound
-    # BF16 + refinement promises; every instance must converge
+    # the exact LP optima (oracle, certified) of 8 instances of the 4800 x 2100
+    # workload -- the five most corrupted (~50 %), two at 35 %, one at 10 % --
+    # solved in one batch with FP32 products, every instance converged and
+    # within the FP32 path's bound
     g = _c4_golden()
     idx = [int(j) for j in g["idx"]]
     B = cab_dictionary(4800, 300, 7, cfg=4)
     b = np.concatenate([cab_instances(B, 1, 7, frac="uneven", cfg=4, first=j)[0] for j in idx], axis=1)
-    pl = _plan(B, structure="cab", precision="bf16_refine", max_batch=len(idx))
-    r = pl.solve(torch.as_tensor(b, device="cuda"), tol=4e-6, max_iter=200000)
+    pl = _plan(B, structure="cab", precision="fp32", max_batch=len(idx))
+    r = pl.solve(torch.as_tensor(b, device="cuda"), tol=4e-6, max_iter=40000)
     st = _np(r.status)
     assert np.all(st == 0), (st, _np(r.iters))
     X, E = _np(r.x), _np(r.e)
     W = np.vstack([X, E])
-    assert_solution_close(X, g["w"][:2100], 1e-3, what="x")
-    assert_solution_close(W, g["w"], 1e-3, what="w")
+    assert_solution_close(X, g["w"][:2100], 1e-4, what="x")
+    assert_solution_close(W, g["w"], 1e-4, what="w")
 
 
 def test_cab_4800x2100_n2048():
     # B 4800 x 2100, A = [B, I] (n = 6900), 2048 instances with corruption
-    # U[0, 0.5], in the benchmark's launch configuration: every instance
-    # converges and sits within the bound of its planted solution (the LP
-    # optimum equals the planted x0 to 1e-7 on the golden instances, up to
-    # 50 % corruption); the golden instances element by element
+    # U[0, 0.5], in the benchmark's launch configuration (FP32 products):
+    # every instance converges and sits within the FP32 bound of its planted
+    # solution (the LP optimum equals the planted x0 to 1e-7 on the golden
+    # instances, up to 50 % corruption); the golden instances element by
+    # element
+    import time
     P = cab_problem(m=4800, classes=300, per_class=7, N=2048, frac="uneven", cfg=4)
-    pl = _plan(P.A, structure="cab", precision="bf16_refine", max_batch=P.N)
+    pl = _plan(P.A, structure="cab", precision="fp32", max_batch=P.N)
     b = torch.as_tensor(P.b, device="cuda")
-    r = pl.solve(b, tol=4e-6, max_iter=200000)
+    t = time.time()
+    r = pl.solve(b, tol=4e-6, max_iter=40000)
     st = _np(r.status)
+    print(f"4800 x 2100, 2048 instances: {time.time() - t:.1f} s, status {np.bincount(st.astype(int), minlength=4)}, "
+          f"iterations max {int(_np(r.iters).max())}", flush=True)
     assert np.all(st == 0), np.bincount(st.astype(int))
     X = _np(r.x)
     err = rel_err_cols(X, P.x0)
-    assert err.max() < 1e-3, (int(err.argmax()), err.max())
+    assert err.max() < 1e-4, (int(err.argmax()), err.max())
     g = _c4_golden()
     for k, j in enumerate(g["idx"]):
-        assert_solution_close(X[:, j], g["w"][:2100, k], 1e-3, what=f"x of instance {j}")
+        assert_solution_close(X[:, j], g["w"][:2100, k], 1e-4, what=f"x of instance {j}")
     rep = pl.kkt(b, r.x, e=r.e, y=r.y).cpu().numpy()
     assert rep[:, 0].max() < 3e-5 and rep[:, 1].max() < 2e-3 and rep[:, 3].max() < 1e-3
 
