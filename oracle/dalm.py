@@ -30,7 +30,15 @@ Readings of points the paper leaves open:
   ``v = A^T y``.  Since ``w_k - w_{k-1} = -beta (z_k - A^T y_k)``, the first
   test is ``beta0 ||z_k - A^T y_k|| <= tol ||w_k||``: the relative-change
   rule the paper uses in Sec. VI-C, measured at the penalty beta0 whatever
-  penalty runs, so the stopping point does not move with beta.  The second test
+  penalty runs, so the stopping point does not move with beta.  For the
+  cross-and-bouquet form the gap is measured against
+  ``max(||w||_1, ||b||_1 / 4)``: every optimum has ``||w*||_1 <= ||b||_1``
+  (``[0; b]`` is feasible), and the floor holds an instance with little
+  corruption (small ||w||_1) to an absolute gap no smaller than the
+  rounding of finite-precision iterates leaves in it: each off-support
+  entry of w carries beta times the rounding of v, and with beta a fixed
+  fraction of ||b||_1 / m their sum is a fixed fraction of ||b||_1.  The
+  second test
   keeps the iteration from stopping on the initial plateau where no clamp is
   active: there w stays at the minimum-norm solution while y grows linearly,
   so the relative change of w is zero but the gap is ``||w||_1``.  For (P1)
@@ -100,7 +108,7 @@ class DalmResult:
 
 
 def _dalm_one(Af, b, beta, tol, max_iter, lam, eps, n_dict, problem,
-              w0, y0, fixed, record, y_step="exact"):
+              w0, y0, fixed, record, y_step="exact", gap_floor=0.0):
     m, n = Af.shape
     dscale = beta_scale(b) / beta if y_step == "exact" else 1.0
     if y_step == "exact":
@@ -147,7 +155,7 @@ def _dalm_one(Af, b, beta, tol, max_iter, lam, eps, n_dict, problem,
         if not (np.isfinite(nw) and np.isfinite(gap)):
             status = NONFINITE
             break
-        if fixed is None and dscale * dw <= tol * nw and gap <= tol * wl1:
+        if fixed is None and dscale * dw <= tol * nw and gap <= tol * max(wl1, gap_floor):
             status = CONVERGED
             break
     if fixed is not None and status != NONFINITE:
@@ -202,7 +210,8 @@ def dalm(A, b, *, structure="dense", problem="p1", beta=None, lam=None, eps=None
             lam, None if eps_arr is None else eps_arr[j], n_dict, problem,
             None if w0 is None else np.asarray(w0)[:, j],
             None if y0 is None else np.asarray(y0)[:, j],
-            fixed_iters, record, y_step)
+            fixed_iters, record, y_step,
+            0.25 * np.abs(b[:, j]).sum() if (structure == "cab" and problem == "p1") else 0.0)
         W[:, j], Y[:, j], V[:, j], its[j], st[j] = w, y, v, k, s
         hist.append(h)
     return DalmResult(W, Y, V, its, st, betas, hist)

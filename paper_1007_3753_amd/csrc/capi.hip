@@ -264,7 +264,7 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   p->zscale = dalloc<float>(Np, o);
   p->tscal = dalloc<float>(Np * 4, o);
   p->wcap2 = dalloc<float>(Np, o);
-  p->dscale2 = dalloc<float>(Np, o);
+  p->dscale2 = dalloc<float>(2 * Np, o);
   const int ntiles = rows / TILE;
   p->ntiles = ntiles;
   p->partial = dalloc<float>((size_t)2 * ntiles * NPART * Np, o);  // two buffers

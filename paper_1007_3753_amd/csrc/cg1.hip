@@ -217,7 +217,7 @@ void solve_dalm_cg1(Plan* p, const SolveArgs& sa) {
   L1_HIP(hipMemsetAsync(p->bb, 0, sizeof(float) * ldm * N, s));
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * ldm, sa.b, sizeof(float) * sa.ldb, sizeof(float) * m, N,
                           hipMemcpyDeviceToDevice, s));
-  penalties(s, N, m, p->bb, ldm, sa.pen, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0, 1.0f, div_factor(p),
+  penalties(s, N, m, p->bb, ldm, sa.pen, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0, 1.0f, 0.0f, div_factor(p),
             p->pen, p->ipen, p->wcap2, nullptr);
   L1_HIP(hipMemsetAsync(p->W, 0, sizeof(float) * (size_t)lds * N, s));
   L1_HIP(hipMemsetAsync(p->V, 0, sizeof(float) * (size_t)lds * N, s));

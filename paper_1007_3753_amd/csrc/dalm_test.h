@@ -14,6 +14,7 @@ struct TestParams {
   float wcap2;           // ||w||^2 above this: L1_DIVERGED (with tol >= 0 only)
   float dscale2;         // (beta0 / beta)^2: ||dw||^2 = beta^2 ||z - v||^2 is tested
                          // as beta0^2 ||z - v||^2 (beta0 = ||b||_1 / m)
+  float gfloor;          // the gap is tested against tol * max(||w||_1, gfloor)
 };
 
 // Sums of the per-row-tile partials of column c, taken by 4 cooperating lanes
@@ -42,7 +43,7 @@ __device__ inline void column_sums(const float* partial, int ldp, int ntiles, in
 // means finished, with *status set to L1_CONVERGED or L1_NONFINITE.
 //   sums: ||dw||^2, ||w||^2, ||w||_1, sum |w|(1 - sign(w) v), ||s_ball||^2
 __device__ inline int decide(const TestParams& tp, int st, const float (&sm)[NPART], int* status) {
-  const float d2 = sm[0] * tp.dscale2, w2 = sm[1], l1 = sm[2], gap = fabsf(sm[3]);
+  const float d2 = sm[0] * tp.dscale2, w2 = sm[1], l1 = fmaxf(sm[2], tp.gfloor), gap = fabsf(sm[3]);
   if (!(isfinite(d2) && isfinite(w2) && isfinite(gap))) {
     *status = L1_NONFINITE;
     return NPHASE;

@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   const int tcol = colidx[tsl];
   const bool tload = test && tcol >= 0 && a.prev_partial != nullptr;
   int st0 = NPHASE, ar0 = 0;
-  float wcap = INFINITY, dsc = 1.0f;
+  float wcap = INFINITY, dsc = 1.0f, gfl = 0.0f;
   float tv[TEST_PRE][NPART];
   if (test) {
     // unconditional loads from clamped addresses (values masked when summed)
@@ -319,7 +319,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     st0 = a.state_in[cc];
     ar0 = a.arith_in ? a.arith_in[cc] : NPHASE;
     if (a.wcap2) wcap = a.wcap2[cc];
-    if (a.dscale2) dsc = a.dscale2[cc];
+    if (a.dscale2) {
+      dsc = a.dscale2[2 * cc];
+      gfl = a.dscale2[2 * cc + 1];
+    }
 #pragma unroll
     for (int i = 0; i < TEST_PRE; ++i) {
       const int t = min(tpart + 4 * i, RT - 1);
@@ -378,6 +381,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     asm volatile("" : "+v"(ar0));
     asm volatile("" : "+v"(wcap));
     asm volatile("" : "+v"(dsc));
+    asm volatile("" : "+v"(gfl));
 #pragma unroll
     for (int i = 0; i < TEST_PRE; ++i)
 #pragma unroll
@@ -418,6 +422,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       tp.final_phase = a.tp_final;
       tp.wcap2 = wcap;
       tp.dscale2 = dsc;
+      tp.gfloor = gfl;
 #pragma unroll
       for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.tp_floor[q];
       st = decide_in(tp, st0, ar0, sm, &stat_new);

@@ -334,7 +334,7 @@ void solve_palm(Plan* p, const SolveArgs& sa) {
   L1_HIP(hipMemsetAsync(p->bb, 0, sizeof(float) * ldm * N, s));
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * ldm, sa.b, sizeof(float) * sa.ldb,
                           sizeof(float) * m, N, hipMemcpyDeviceToDevice, s));
-  penalties(s, N, m, p->bb, ldm, sa.pen, p->d.xi > 0 ? (float)p->d.xi : 0.0f, 1, 1.0f, div_factor(p),
+  penalties(s, N, m, p->bb, ldm, sa.pen, p->d.xi > 0 ? (float)p->d.xi : 0.0f, 1, 1.0f, 0.0f, div_factor(p),
             p->pen, p->ipen, p->wcap2, nullptr);
   float* eps = nullptr;
   if (p->d.problem == L1_P12) {

@@ -103,9 +103,15 @@ struct SolveArgs {
 // cross-and-bouquet form, 1 for dense dictionaries.  On face-shaped problems
 // the smaller penalty reaches a given error in several times fewer
 // iterations on the slowest instances (as many on the others); on Gaussian
-// dictionaries beta0 is the faster one.
-inline float default_beta_scale(const Plan* p) {
-  return (p->d.structure == L1_CAB) ? 0.125f : 1.0f;
+// dictionaries beta0 is the faster one.  The smaller penalty enlarges the
+// operand u = z - (w - w_ref)/beta until its reference is refreshed, which
+// happens only while two or more column tiles are active: with BF16
+// products a batch of N <= 64 keeps beta0 (its split-BF16 rounding would
+// stall the stopping test).
+inline float default_beta_scale(const Plan* p, int N) {
+  if (p->d.structure != L1_CAB) return 1.0f;
+  if (p->d.precision != L1_FP32 && N <= TILE) return 1.0f;
+  return 0.125f;
 }
 
 // L1_DIVERGED threshold factor of the plan (desc.div_factor, default 1e6)

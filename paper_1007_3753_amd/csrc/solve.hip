@@ -120,7 +120,8 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   L1_HIP(hipMemcpy2DAsync(p->bb, sizeof(float) * p->m_pad, a.b, sizeof(float) * a.ldb,
                           sizeof(float) * m, N, hipMemcpyDeviceToDevice, s));
   penalties(s, N, m, p->bb, p->m_pad, a.pen, p->d.beta > 0 ? (float)p->d.beta : 0.0f, 0,
-            default_beta_scale(p), div_factor(p), p->pen, p->ipen, p->wcap2, p->dscale2);
+            default_beta_scale(p, N), p->split && p->d.problem == L1_P1 ? 0.25f : 0.0f, div_factor(p),
+            p->pen, p->ipen, p->wcap2, p->dscale2);
   {
     GemmArgs g{};
     g.A32 = p->Cop;

@@ -47,7 +47,7 @@ struct DalmCheck {
   const float* eps;      // P_{1,2} radii
   const float* beta;
   const float* wcap2;    // squared L1_DIVERGED thresholds (null: no test)
-  const float* dscale2;  // (beta0 / beta)^2 per instance (null: 1)
+  const float* dscale2;  // per instance {(beta0 / beta)^2, gap-scale floor} (null: {1, 0})
   long long* stat;       // [7] = largest per-instance iteration count
 };
 
@@ -69,12 +69,13 @@ struct P12Fix {
 // Per-instance penalty from pen_in[c] when it is positive and finite, else
 // `fixed` when > 0, else the default of the instance: mode 0 (DALM) beta =
 // dflt ||b||_1 / m, mode 1 (PALM) xi = 2 m / ||b||_1; the squared
-// L1_DIVERGED threshold (div sqrt(m) ||b||_2)^2; and dscale2 = (beta0 /
-// beta)^2 with beta0 = ||b||_1 / m, the unit of the DALM stopping test (may
-// be null).
+// L1_DIVERGED threshold (div sqrt(m) ||b||_2)^2; and per instance the pair
+// dscale2[2c] = (beta0 / beta)^2 with beta0 = ||b||_1 / m, the unit of the
+// DALM stopping test, and dscale2[2c + 1] = gfl ||b||_1, the floor of its gap
+// scale (may be null).
 void penalties(hipStream_t s, int N, int m, const float* b, int ldb, const float* pen_in,
-               float fixed, int mode, float dflt, float div, float* pen, float* ipen, float* wcap2,
-               float* dscale2);
+               float fixed, int mode, float dflt, float gfl, float div, float* pen, float* ipen,
+               float* wcap2, float* dscale2);
 void dalm_init_u(hipStream_t s, int N, const DalmInit& a);
 void init_lists(hipStream_t s, int N, int phase0, const Lists& L, int* state_other,
                 long long* stat);

@@ -42,8 +42,8 @@ __device__ float wg_sum(float v, float* sh) {
 // replaces the plan's value and the default
 __global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int ldb,
                                                       const float* pen_in, float fixed, int mode,
-                                                      float dflt, float div, float* pen, float* ipen,
-                                                      float* wcap2, float* dscale2) {
+                                                      float dflt, float gfl, float div, float* pen,
+                                                      float* ipen, float* wcap2, float* dscale2) {
   __shared__ float sh[256];
   const int c = blockIdx.x;
   float s = 0.0f, s2 = 0.0f;
@@ -65,14 +65,20 @@ __global__ __launch_bounds__(256) void penalty_kernel(int m, const float* b, int
     pen[c] = p;
     ipen[c] = 1.0f / p;
     if (wcap2) wcap2[c] = div * div * (float)m * s2;
-    if (dscale2) dscale2[c] = (beta0 / p) * (beta0 / p);
+    if (dscale2) {
+      // pair per instance: the stopping test's (beta0 / beta)^2, and the
+      // floor of its gap scale (||b||_1 / 4 for the cross-and-bouquet form)
+      dscale2[2 * c] = (beta0 / p) * (beta0 / p);
+      dscale2[2 * c + 1] = gfl * s;
+    }
   }
 }
 void penalties(hipStream_t s, int N, int m, const float* b, int ldb, const float* pen_in,
-               float fixed, int mode, float dflt, float div, float* pen, float* ipen, float* wcap2,
-               float* dscale2) {
+               float fixed, int mode, float dflt, float gfl, float div, float* pen, float* ipen,
+               float* wcap2, float* dscale2) {
   if (N <= 0) return;
-  penalty_kernel<<<N, 256, 0, s>>>(m, b, ldb, pen_in, fixed, mode, dflt, div, pen, ipen, wcap2, dscale2);
+  penalty_kernel<<<N, 256, 0, s>>>(m, b, ldb, pen_in, fixed, mode, dflt, gfl, div, pen, ipen, wcap2,
+                                   dscale2);
   L1_HIP(hipGetLastError());
 }
 
@@ -215,7 +221,8 @@ __global__ __launch_bounds__(256) void dalm_final_test_kernel(DalmCheck a) {
   tp.final_phase = a.final_phase;
   for (int q = 0; q < NPHASE; ++q) tp.floor[q] = a.floor[q];
   tp.wcap2 = a.wcap2 ? a.wcap2[c] : INFINITY;
-  tp.dscale2 = a.dscale2 ? a.dscale2[c] : 1.0f;
+  tp.dscale2 = a.dscale2 ? a.dscale2[2 * c] : 1.0f;
+  tp.gfloor = a.dscale2 ? a.dscale2[2 * c + 1] : 0.0f;
   int status = L1_MAXITER;
   const int st = decide_in(tp, st0, a.arith ? a.arith[c] : NPHASE, sm, &status);
   if (st != st0) a.L.state[c] = st;

@@ -346,7 +346,8 @@ __global__ __launch_bounds__(256) void dalm_tail_kernel(TailArgs a) {
         const int ar = (first && a.reg_arith) ? a.reg_arith[s_col[j]] : NPHASE;
         TestParams tp = a.tp;
         tp.wcap2 = a.wcap2 ? a.wcap2[s_col[j]] : INFINITY;
-        tp.dscale2 = a.dscale2 ? a.dscale2[s_col[j]] : 1.0f;
+        tp.dscale2 = a.dscale2 ? a.dscale2[2 * s_col[j]] : 1.0f;
+        tp.gfloor = a.dscale2 ? a.dscale2[2 * s_col[j] + 1] : 0.0f;
         const int st = decide_in(tp, s_st[j], ar, sm, &stat_new);
         if (g == 0) {
           if (st >= NPHASE) a.status[s_col[j]] = stat_new;
