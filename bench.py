@@ -80,9 +80,9 @@ def dalm_roofline(m, n_dict, structure, agg, kern_s, launches):
 
 WORKLOADS = {
     # B 1200 x 700 (100 classes x 7), A = [B, I]; 512 test vectors, 30 % corrupted
-    "cab-1200x700-n512": dict(m=1200, classes=100, per_class=7, N=512, frac=0.3, cfg=3, precision="fp32"),
+    "cab-1200x700-n512": dict(m=1200, classes=100, per_class=7, N=512, frac=0.3, cfg=3, precision="bf16_refine"),
     # B 4800 x 2100 (300 classes x 7); 2048 test vectors, corruption U[0, 0.5] each
-    "cab-4800x2100-n2048": dict(m=4800, classes=300, per_class=7, N=2048, frac="uneven", cfg=4, precision="fp32"),
+    "cab-4800x2100-n2048": dict(m=4800, classes=300, per_class=7, N=2048, frac="uneven", cfg=4, precision="bf16_refine"),
 }
 DEFAULT_WORKLOAD = "cab-1200x700-n512"
 # The paper's noise-free synthetic benchmark (Sec. VI-A): m = 800, Gaussian A with
@@ -124,7 +124,7 @@ def parse():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + sorted(E1_WORKLOADS) + sorted(ALIGN_WORKLOADS)
                     + sorted(QP_WORKLOADS) + sorted(UNROLLED_WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16_refine", "bf16x3"],
-                    help="default: fp32 (the cross-and-bouquet workloads and e1-*)")
+                    help="default: bf16_refine for the cross-and-bouquet workloads, fp32 for e1-*")
     ap.add_argument("--method", default="dalm", choices=["dalm", "palm", "adm", "dalm_cg1"],
                     help="e1-* workloads only (the cross-and-bouquet benchmark is DALM)")
     ap.add_argument("--e1-instances", type=int, default=20)
@@ -373,21 +373,21 @@ def main():
                           f"Cholesky y-step, same tol ({args.tol:g}); {dt:.1f} s, iterations "
                           f"{o.iters.tolist()}; the rate extrapolates to the batch"}
             log(f"CPU oracle: {k} instances in {dt:.1f} s on {threads} threads")
-            # ground truth (not timed for ranking): instance 0 to tol 1e-10
-            # (at most 30000 iterations) with its FP64 certificate, and the
-            # GPU result against it
-            log("CPU ground truth: oracle DALM on instance 0 to tol 1e-10 ...")
+            # ground truth (not timed for ranking): the exact LP optimum of
+            # instance 0 (oracle, simplex/interior point in FP64) with its FP64
+            # certificate, and the GPU result against it
+            from oracle import p1_lp
             t = time.perf_counter()
-            g = oracle_dalm(P.A, P.b[:, :1], structure="cab", tol=1e-10, max_iter=30000)
+            Af = full_matrix(P.A, "cab")
+            wg, yg = p1_lp(Af, P.b[:, 0])
             gdt = time.perf_counter() - t
-            rep0 = kkt_report(full_matrix(P.A, "cab"), P.b[:, 0], g.w[:, 0], g.y[:, 0])
-            xg = g.w[:nd, 0]
+            rep0 = kkt_report(Af, P.b[:, 0], wg, yg)
+            xg = wg[:nd]
             out["cpu_ground_truth"] = {
-                "instance": 0, "tol": 1e-10, "iterations": int(g.iters[0]), "status": int(g.status[0]),
-                "s": round(gdt, 2),
+                "instance": 0, "solver": "exact LP (oracle.p1_lp)", "s": round(gdt, 2),
                 "kkt": rep0, "gpu_rel_err": float(np.linalg.norm(X[:, 0] - xg) / np.linalg.norm(xg))}
-            log(f"CPU ground truth (instance 0, tol 1e-10): {int(g.iters[0])} iterations, {gdt:.1f} s, "
-                f"KKT {rep0}; GPU rel. err {out['cpu_ground_truth']['gpu_rel_err']:.2e}")
+            log(f"CPU ground truth (instance 0, exact LP): {gdt:.1f} s, KKT {rep0}; "
+                f"GPU rel. err {out['cpu_ground_truth']['gpu_rel_err']:.2e}")
         else:
             # a solve of this size takes minutes on the host: 100 iterations of
             # instance 0, extrapolated to the batch's mean iteration count
