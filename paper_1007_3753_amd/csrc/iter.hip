@@ -313,16 +313,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   float wcap = INFINITY, dsc = 1.0f, gfl = 0.0f;
   float tv[TEST_PRE][NPART];
   if (test) {
-    // unconditional loads from clamped addresses (values masked when summed)
+    // unconditional loads from clamped addresses (values masked when
+    // summed); an absent per-instance array reads a stand-in (the partial
+    // sums, at least 2N long) whose value is replaced after the K loop, so
+    // that no load result is consumed (and waited for) before the K loop
     const float* pp = a.prev_partial ? a.prev_partial : a.partial;
     const int cc = tcol >= 0 ? tcol : 0;
     st0 = a.state_in[cc];
-    ar0 = a.arith_in ? a.arith_in[cc] : NPHASE;
-    if (a.wcap2) wcap = a.wcap2[cc];
-    if (a.dscale2) {
-      dsc = a.dscale2[2 * cc];
-      gfl = a.dscale2[2 * cc + 1];
-    }
+    ar0 = (a.arith_in ? a.arith_in : a.state_in)[cc];
+    wcap = (a.wcap2 ? a.wcap2 : pp)[cc];
+    dsc = (a.dscale2 ? a.dscale2 : pp)[2 * cc];
+    gfl = (a.dscale2 ? a.dscale2 : pp)[2 * cc + 1];
 #pragma unroll
     for (int i = 0; i < TEST_PRE; ++i) {
       const int t = min(tpart + 4 * i, RT - 1);
@@ -336,6 +337,28 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f4{0.f, 0.f, 0.f, 0.f};
+  // DALM: the epilogue's state loads are issued here, so that their memory
+  // round trip overlaps the K loop instead of following it (measured on the
+  // 1200 x 700 cross-and-bouquet batch of 512: epilogue 5.6 -> 3.9 us per
+  // launch); the K loop's waits cover them, being younger
+  f4 pre_c[2][2], pre_w[2][2], pre_v[2][2], pre_r[2][2];
+  if (EPI == EPI_DALM) {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int cc = colidx[wn * 32 + bj * 16 + li];
+      const long cb = (long)(cc >= 0 ? cc : 0) * a.lds;   // idle slots read column 0, never stored
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const long idx = cb + i0 + wm * 32 + bi * 16 + 4 * q;
+        pre_c[bi][bj] = *reinterpret_cast<const f4*>(a.C + idx);
+        pre_w[bi][bj] = *reinterpret_cast<const f4*>(a.W + idx);
+        pre_v[bi][bj] = *reinterpret_cast<const f4*>(a.V + idx);
+        pre_r[bi][bj] = a.Wref ? *reinterpret_cast<const f4*>(a.Wref + idx) : f4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
   {
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
@@ -386,6 +409,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     for (int i = 0; i < TEST_PRE; ++i)
 #pragma unroll
       for (int q = 0; q < NPART; ++q) asm volatile("" : "+v"(tv[i][q]));
+    if (!a.arith_in) ar0 = NPHASE;
+    if (!a.wcap2) wcap = INFINITY;
+    if (!a.dscale2) {
+      dsc = 1.0f;
+      gfl = 0.0f;
+    }
     float sm[NPART];
 #pragma unroll
     for (int q = 0; q < NPART; ++q) sm[q] = 0.0f;
@@ -494,8 +523,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     for (int bi = 0; bi < 2; ++bi) {
       const int row0 = i0 + wm * 32 + bi * 16 + 4 * q;
       const long idx = (long)col * a.lds + row0;
-      const f4 c4 = *reinterpret_cast<const f4*>(a.C + idx);
-      const f4 wo = *reinterpret_cast<const f4*>(a.W + idx);
+      const f4 c4 = EPI == EPI_DALM ? pre_c[bi][bj] : *reinterpret_cast<const f4*>(a.C + idx);
+      const f4 wo = EPI == EPI_DALM ? pre_w[bi][bj] : *reinterpret_cast<const f4*>(a.W + idx);
       f4 wn4, un4;
       if (EPI == EPI_REFRESH) {
         // w_ref = w, c_ref = (C0 - P w) / beta, and the next operand
@@ -528,8 +557,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         const float bt = a.beta[col];
         const float ib = 1.0f / bt;
         const float zsc = s_zsc[wn * 32 + bj * 16 + li];
-        const f4 vo = *reinterpret_cast<const f4*>(a.V + idx);
-        const f4 wr4 = a.Wref ? *reinterpret_cast<const f4*>(a.Wref + idx) : f4{0.f, 0.f, 0.f, 0.f};
+        const f4 vo = pre_v[bi][bj];
+        const f4 wr4 = pre_r[bi][bj];
         f4 vn4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
