@@ -45,6 +45,16 @@ def dalm_work_model(m, n_dict, structure):
             "state": 4.0 * (4 * n + 5 * m + 2 * n_dict)}
 
 
+def dalm_structured_model(m, n_dict):
+    """The same for the structured (Woodbury) y-step of the cross-and-bouquet
+    form with n_B < m: B and B^T once each and the n_B x n_B inverse of
+    K = I + B^T B, all in the product's arithmetic:
+        flops   F = 4 m n_B + 2 n_B^2
+        matrix  (2 m n_B + n_B^2) s."""
+    return {"flops": 4.0 * m * n_dict + 2.0 * n_dict * n_dict,
+            "matrix": lambda s: (2.0 * m * n_dict + 1.0 * n_dict * n_dict) * s}
+
+
 def dalm_roofline(m, n_dict, structure, agg, kern_s, launches):
     """Roofline of the DALM iteration over a timed run: instance-iterations
     by arithmetic (agg cols_*), iterations of the slowest instance (one
@@ -54,9 +64,21 @@ def dalm_roofline(m, n_dict, structure, agg, kern_s, launches):
     wm = dalm_work_model(m, n_dict, structure)
     cols = {"fp32": agg["cols_fp32"], "bf16": agg["cols_bf16"], "split": agg["cols_split"]}
     tot_cols = max(sum(cols.values()), 1.0)
+    # instance-iterations of the structured form (FP32 or BF16 tiles only):
+    # counted at its own flops and matrix bytes
+    c_st = min(agg.get("cols_structured", 0.0), cols["fp32"] + cols["bf16"])
+    f_st = c_st / tot_cols
+    ws = dalm_structured_model(m, n_dict)
     flops = {k: wm["flops"] * c for k, c in cols.items()}
+    if c_st > 0:
+        # split the structured share between FP32 and BF16 in proportion
+        nb = cols["fp32"] + cols["bf16"]
+        for k in ("fp32", "bf16"):
+            share = c_st * cols[k] / nb
+            flops[k] += (ws["flops"] - wm["flops"]) * share
     s_avg = sum(ELEM_BYTES[k] * c for k, c in cols.items()) / tot_cols
-    bytes_total = agg["iterations"] * wm["matrix"](s_avg) + wm["state"] * tot_cols
+    bytes_total = (agg["iterations"] * ((1.0 - f_st) * wm["matrix"](s_avg) + f_st * ws["matrix"](s_avg))
+                   + wm["state"] * tot_cols)
     tot_flops = sum(flops.values())
     t_mfma = sum(flops[k] / (PEAK_TFLOPS[k] * 1e12) for k in flops)
     t_hbm = bytes_total / (PEAK_HBM_GBS * 1e9)
@@ -125,6 +147,8 @@ def parse():
                     + sorted(QP_WORKLOADS) + sorted(UNROLLED_WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16_refine", "bf16x3"],
                     help="default: bf16_refine for the cross-and-bouquet workloads, fp32 for e1-*")
+    ap.add_argument("--form", default="auto", choices=["auto", "dense", "structured"],
+                    help="DALM iteration form of the cross-and-bouquet workloads (include/l1_alm.h)")
     ap.add_argument("--method", default="dalm", choices=["dalm", "palm", "adm", "dalm_cg1"],
                     help="e1-* workloads only (the cross-and-bouquet benchmark is DALM)")
     ap.add_argument("--e1-instances", type=int, default=20)
@@ -202,7 +226,8 @@ def main():
     b = torch.as_tensor(P.b, device=dev)
     m, nd, N = P.m, P.n_dict, P.N
     n_full = nd + m
-    plan = Plan(A, structure="cab", precision=args.precision, max_batch=N, time_kernels=True)
+    plan = Plan(A, structure="cab", precision=args.precision, max_batch=N, time_kernels=True,
+                iteration_form=args.form)
     plan_ms = plan.last_stats()["plan_ms"]
     log(f"plan ({args.precision}) built in {plan_ms:.1f} ms")
     # launch shape: the split-K table from the autotuner (run here with
@@ -229,7 +254,7 @@ def main():
         log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     agg = dict(timed_ms=0.0, timed_launches=0.0, launch_fp32=0.0, launch_bf16=0.0, launch_split=0.0,
-               cols_fp32=0.0, cols_bf16=0.0, cols_split=0.0, iterations=0.0)
+               cols_fp32=0.0, cols_bf16=0.0, cols_split=0.0, iterations=0.0, cols_structured=0.0)
     t_start = time.perf_counter()
     for i in range(args.steps):
         r, rep = step()
@@ -255,8 +280,11 @@ def main():
     roof["traffic"] = None if trec is None else trec.get("hbm_bytes_per_launch_at_workload", {}).get(args.workload)
     roof.update({
         "kernel": "DALM iteration: gemm_kernel<EPI_DALM> (+ its split-K gemm_kernel<EPI_PARTIAL> "
-                  "launch when few column tiles are active, + 1/16 of a compaction), or one "
+                  "launch when few column tiles are active, + 1/16 of a compaction; two "
+                  "gemm_kernel<EPI_DALM> launches in the structured form), or one "
                   "iteration of dalm_tail_kernel once few instances are left",
+        "structured_share": round(agg["cols_structured"] / max(agg["cols_fp32"] + agg["cols_bf16"]
+                                                                + agg["cols_split"], 1.0), 3),
         "kernel_share_of_step": round(agg["timed_ms"] / (ms_per_step * args.steps), 3),
     })
     log(f"iteration kernel: {nl:.0f} launches, avg {1e6 * kern_s / nl:.2f} us; "
@@ -273,7 +301,8 @@ def main():
         "data": "synthetic (seeded cross-and-bouquet stand-in for face images; no dataset)",
         "config": {"workload": args.workload, "m": m, "n_dict": nd, "n_full": n_full, "N": N,
                    "problem": "P1", "structure": "cab", "method": "dalm",
-                   "precision": args.precision, "tol": args.tol, "max_iter": args.max_iter},
+                   "precision": args.precision, "tol": args.tol, "max_iter": args.max_iter,
+                   "iteration_form": args.form},
         "plan_ms": round(plan_ms, 2),
         "ksplit": ks_info,
         "iterations": {"mean": float(iters.mean()), "max": int(iters.max())},

@@ -95,8 +95,10 @@ typedef struct {
   int precision;         /* l1_precision                                             */
   int max_batch;         /* upper bound on N for every solve with this plan (>= 1)   */
   double lambda;         /* QP_lambda weight (> 0); ignored otherwise                */
-  double beta;           /* DALM penalty.  <= 0: per instance ||b||_1 / m.  Required
-                            (> 0) for DALM on QP_lambda, where it enters the factor. */
+  double beta;           /* DALM penalty.  <= 0: per instance beta0 = ||b||_1 / m, and
+                            beta0 / 8 for L1_CAB (L1_FP32 plans, or batches of more
+                            than 64 instances).  Required (> 0) for DALM on
+                            QP_lambda, where it enters the factor.                   */
   double xi;             /* PALM penalty.  <= 0: per instance 2 m / ||b||_1 (Sec. V-A) */
   double xi_growth;      /* PALM: xi <- xi * xi_growth after each outer step (<= 0 -> 1) */
   int max_inner;         /* PALM: cap on FISTA steps per outer step (<= 0 -> 100)     */
@@ -107,7 +109,35 @@ typedef struct {
   int time_kernels;      /* 1: time the DALM iteration loop with HIP events on the
                             solve stream (see l1_alm_last_stats)                    */
   double div_factor;     /* L1_DIVERGED threshold factor (<= 0 -> 1e6)               */
+  int iteration_form;    /* L1_DALM on L1_CAB (P1) with n_dict < m, or on L1_DENSE with
+                            m < n_dict: 0 automatic, 1 the dense operator only, 2 the
+                            structured form whenever it applies ("Iteration forms") */
 } l1_alm_desc;
+
+/* Iteration forms of L1_DALM on the cross-and-bouquet (P1).  Sec. V-B makes
+ * the y-step (A A^T)^{-1} applied to a vector; with A = [B, I] the Woodbury
+ * identity gives (B B^T + I)^{-1} = I - B K^{-1} B^T, K = I + B^T B.  The
+ * dense form multiplies u by P = A^T (A A^T)^{-1} A (n x n) every iteration.
+ * The structured form takes the first n_dict rows of P u (an n_dict x n
+ * product), forms q = u_x - (P u)_x = K^{-1} (u_x - B^T u_e), and then
+ * (P u)_e = u_e + B q (an m x n_dict product): 2 n_dict (n + m) flops and
+ * operator bytes per instance instead of 2 n^2, in two launches instead of
+ * one.  Both forms give the same iterates up to rounding, but the second
+ * product carries the rounding of the first through B (||B|| ~ 30 on face
+ * dictionaries).  It runs BF16 and FP32 tiles (split-BF16 tiles stay dense:
+ * their 16 bits would miss the 1e-4 accuracy of the converged solution).
+ * Automatic mode uses it for L1_FP32 plans while the unfinished instances
+ * span at least 16 column tiles of 64 (the products, not the per-launch
+ * latency, then set the time; the last instances converge densely, since
+ * the amplified rounding can hold the relative change of w above the
+ * stopping threshold) and when the structured products cost at most 0.8 of
+ * the dense one.  On a dense dictionary with m < n_dict the y-step's factor
+ * is applied the same way: t = (A A^T + shift I)^{-1} A u (an m x n_dict
+ * product), then v = A^T t + c (n_dict x m): 4 m n_dict instead of
+ * 2 n_dict^2, under the same automatic rule (A^T spreads the first
+ * product's rounding by ||A||, 3 for a Gaussian 2000 x 8000 dictionary).
+ * The tail of few instances, the FP32 refresh of the operand's reference
+ * point and recorded tapes use the dense form.                              */
 
 /* Build a plan for the dictionary A_dev (m x n_dict, column-major, leading
  * dimension desc->lda >= m).
@@ -187,18 +217,20 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
 /* Statistics of the last l1_alm_solve on this plan; writes min(n, 14)
  * doubles to out (host memory):
  *   [0..2]  column tiles (64 instances) of the per-iteration product that
- *           had work, summed over the launches, by the arithmetic of the
- *           tile: FP32, BF16, split BF16
+ *           had work, summed over the iterations (an iteration of the
+ *           structured form counts once), by the arithmetic of the tile:
+ *           FP32, BF16, split BF16
  *   [3..5]  instances summed over those tiles and launches, by arithmetic
  *   [6]     DALM, desc.time_kernels = 1: duration (ms) of the iteration loop,
  *           from HIP events on the solve stream around every block of 16
  *           iteration launches (with their compaction); else 0
- *   [7]     number of iteration launches inside those blocks
+ *   [7]     number of iterations inside those blocks
  *   [8]     iterations run (the largest per-instance count; PALM: outer steps)
  *   [9]     wall time of the call on the host (ms)
  *   [10]    one-time plan construction time (ms, host wall clock)
  *   [11]    PALM: FISTA product launches issued (summed over outer steps)
- *   [12..13] reserved (0)
+ *   [12]    the part of [3..5] that ran in the structured form
+ *   [13]    reserved (0)
  * The tolerance floors used by the stopping test are FP32 2e-6 and split
  * BF16 4e-6 (the level where rounding noise stalls the test).             */
 int l1_alm_last_stats(l1_alm_plan_t plan, double* out, int n);

@@ -34,6 +34,7 @@ class l1_alm_desc(ctypes.Structure):
         ("tol_inner", ctypes.c_double), ("refine_switch", ctypes.c_double),
         ("record_tape", ctypes.c_int), ("checkpoint_every", ctypes.c_int),
         ("time_kernels", ctypes.c_int), ("div_factor", ctypes.c_double),
+        ("iteration_form", ctypes.c_int),
     ]
 
 

@@ -16,6 +16,7 @@ PROBLEMS = {"p1": 0, "p12": 1, "qp": 2}
 STRUCTURES = {"dense": 0, "cab": 1}
 METHODS = {"dalm": 0, "palm": 1, "dalm_cg1": 2}
 PRECISIONS = {"fp32": 0, "bf16_refine": 1, "bf16x3": 2}
+FORMS = {"auto": 0, "dense": 1, "structured": 2}
 CONVERGED, MAXITER, NONFINITE, DIVERGED = 0, 1, 2, 3
 
 
@@ -57,7 +58,7 @@ class Plan:
     def __init__(self, A, *, problem="p1", structure="dense", method="dalm",
                  precision="fp32", max_batch=1, lam=0.0, beta=0.0, xi=0.0, xi_growth=1.0,
                  max_inner=100, tol_inner=0.0, refine_switch=0.0, record_tape=False,
-                 checkpoint_every=10, time_kernels=False, div_factor=0.0):
+                 checkpoint_every=10, time_kernels=False, div_factor=0.0, iteration_form="auto"):
         self.lib = _lib.load()
         A = torch.as_tensor(A)
         if A.dim() != 2 or not A.is_cuda:
@@ -80,6 +81,7 @@ class Plan:
         d.record_tape, d.checkpoint_every = int(bool(record_tape)), int(checkpoint_every)
         d.time_kernels = int(bool(time_kernels))
         d.div_factor = float(div_factor)
+        d.iteration_form = FORMS[iteration_form]
         self.desc = d
         self._tape_N = 0
         h = ctypes.c_void_p()
@@ -196,7 +198,7 @@ class Plan:
 
     STAT_KEYS = ("launch_fp32", "launch_bf16", "launch_split", "cols_fp32", "cols_bf16",
                  "cols_split", "timed_ms", "timed_launches", "iterations", "solve_ms", "plan_ms",
-                 "inner_iterations")
+                 "inner_iterations", "cols_structured")
 
     def last_stats(self):
         out = (ctypes.c_double * 14)()

@@ -107,6 +107,8 @@ static void build_dalm(Plan* p, hipStream_t s, const double* A64, Scratch& sc, i
     }
     // c = A^T G^{-1} b / beta is the block of P that multiplies the identity part
     to_rowmajor_f32(s, n, m, P64 + (size_t)nd * n, n, p->Cop, p->m_pad, nullptr, nullptr);
+    // structured form: B row-major for the second product
+    if (p->st_ok == 1) to_rowmajor_f32(s, m, nd, A64, m, p->Bq32, p->nd_pad, p->Bqhi, p->Bqlo);
   } else {
     // dense: G = A A^T + shift I = L L^T, X = L^{-1}, T2 = X A,
     // P = T2^T T2, c-operator A^T G^{-1} = T2^T X, y-operator (A A^T)^{-1} A
@@ -134,6 +136,13 @@ static void build_dalm(Plan* p, hipStream_t s, const double* A64, Scratch& sc, i
       gemm64(s, 'T', 'N', m, nd, m, 1.0, X0, m, T0, m, 0.0, Y64, m);
     }
     to_rowmajor_f32(s, m, nd, Y64, m, p->Yop, p->n_pad, nullptr, nullptr);
+    if (p->st_ok == 2) {
+      // structured form: t = G^{-1} A u (G with the shift), then v = A^T t + c
+      double* R64 = sc.d((size_t)m * nd);
+      gemm64(s, 'T', 'N', m, nd, m, 1.0, X, m, T2, m, 0.0, R64, m);
+      to_rowmajor_f32(s, m, nd, R64, m, p->R32, p->n_pad, p->Rhi, p->Rlo);
+      transpose_f64_to_f32(s, nd, m, A64, m, p->Bq32, p->m_pad, p->Bqhi, p->Bqlo);
+    }
   }
   to_rowmajor_f32(s, n, n, P64, n, p->P32, p->n_pad, p->Phi, p->Plo);
 }
@@ -157,6 +166,7 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
   L1_REQUIRE(d->method != L1_DALM_CG1 || (d->problem == L1_P1 && d->precision == L1_FP32),
              "L1_DALM_CG1 runs (P1) with L1_FP32 products");
   L1_REQUIRE(d->precision >= 0 && d->precision <= 2, "unknown precision");
+  L1_REQUIRE(d->iteration_form >= 0 && d->iteration_form <= 2, "unknown iteration form");
   L1_REQUIRE(!(d->structure == L1_CAB && d->problem != L1_P1),
              "QP_lambda and P_{1,2} are defined on a dense dictionary (structure L1_DENSE)");
   L1_REQUIRE(d->problem != L1_QPLAMBDA || d->lambda > 0, "QP_lambda needs lambda > 0");
@@ -220,6 +230,57 @@ Plan* create_plan(const l1_alm_desc* d, const float* A_dev, hipStream_t s) {
     if (!p->split) {
       p->Yop = dalloc<float>((size_t)p->m_pad * p->n_pad, o);
       L1_HIP(hipMemsetAsync(p->Yop, 0, sizeof(float) * p->m_pad * p->n_pad, s));
+    }
+    // structured iteration forms (include/l1_alm.h): cross-and-bouquet (P1)
+    // with n_dict < m, or a dense dictionary with m < n_dict, when its two
+    // products cost at most 0.8 of the dense operator's
+    const double f_dense = 2.0 * p->n_pad * (double)p->n_pad;
+    const int R1 = round_up(nd > 0 ? nd : 1, TILE);
+    size_t nt_rows = 0;
+    if (d->iteration_form != 1 && p->split && d->problem == L1_P1 && nd >= 1 && nd < m &&
+        2.0 * R1 * p->n_pad + 2.0 * (p->n_pad - R1) * (double)p->nd_pad <= 0.8 * f_dense) {
+      // B with TILE spare zero rows: the second launch starts at state row R1,
+      // i.e. at B row R1 - n_dict
+      p->st_ok = 1;
+      p->R1 = R1;
+      p->ldt = p->nd_pad;
+      nt_rows = p->nd_pad;
+      const size_t nb = (size_t)(p->m_pad + TILE) * p->nd_pad;
+      p->Bq32 = dalloc<float>(nb, o);
+      L1_HIP(hipMemsetAsync(p->Bq32, 0, sizeof(float) * nb, s));
+      if (low) {
+        p->Bqhi = dalloc<uint16_t>(nb, o);
+        p->Bqlo = dalloc<uint16_t>(nb, o);
+        L1_HIP(hipMemsetAsync(p->Bqhi, 0, sizeof(uint16_t) * nb, s));
+        L1_HIP(hipMemsetAsync(p->Bqlo, 0, sizeof(uint16_t) * nb, s));
+      }
+    } else if (d->iteration_form != 1 && !p->split && nd >= 1 && m < nd &&
+               4.0 * p->m_pad * (double)p->n_pad <= 0.8 * f_dense) {
+      p->st_ok = 2;
+      p->ldt = p->m_pad;
+      nt_rows = p->m_pad;
+      const size_t nb = (size_t)p->n_pad * p->m_pad;
+      p->Bq32 = dalloc<float>(nb, o);
+      p->R32 = dalloc<float>(nb, o);
+      L1_HIP(hipMemsetAsync(p->Bq32, 0, sizeof(float) * nb, s));
+      L1_HIP(hipMemsetAsync(p->R32, 0, sizeof(float) * nb, s));
+      if (low) {
+        for (uint16_t** q : {&p->Bqhi, &p->Bqlo, &p->Rhi, &p->Rlo}) {
+          *q = dalloc<uint16_t>(nb, o);
+          L1_HIP(hipMemsetAsync(*q, 0, sizeof(uint16_t) * nb, s));
+        }
+      }
+    }
+    if (p->st_ok) {
+      const size_t nt = nt_rows * round_up(d->max_batch, TILE);
+      p->Tf = dalloc<float>(nt, o);
+      L1_HIP(hipMemsetAsync(p->Tf, 0, sizeof(float) * nt, s));
+      if (low) {
+        p->Th = dalloc<uint16_t>(nt, o);
+        p->Tl = dalloc<uint16_t>(nt, o);
+        L1_HIP(hipMemsetAsync(p->Th, 0, sizeof(uint16_t) * nt, s));
+        L1_HIP(hipMemsetAsync(p->Tl, 0, sizeof(uint16_t) * nt, s));
+      }
     }
     build_dalm(p.get(), s, A64, sc, info);
   } else if (d->method == L1_PALM) {

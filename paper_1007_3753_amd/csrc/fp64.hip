@@ -348,19 +348,26 @@ void to_rowmajor_f32(hipStream_t s, int rows, int cols, const double* src, int l
   L1_HIP(hipGetLastError());
 }
 __global__ void copy_rows_f64_to_f32_kernel(int rows, int cols, const double* src, int lds,
-                                            float* dst, int ldd) {
+                                            float* dst, int ldd, uint16_t* hi, uint16_t* lo) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)rows * cols) return;
   const int k = (int)(e % cols), i = (int)(e / cols);
-  dst[(long)i * ldd + k] = (float)src[k + (long)i * lds];
+  const double x = src[k + (long)i * lds];
+  const long o = (long)i * ldd + k;
+  dst[o] = (float)x;
+  if (hi) {
+    const uint16_t h = bf16_rne((float)x);
+    hi[o] = h;
+    lo[o] = bf16_rne((float)(x - (double)bf16_to_f(h)));
+  }
 }
 void transpose_f64_to_f32(hipStream_t s, int rows, int cols, const double* src, int lds,
-                          float* dst, int ldd) {
+                          float* dst, int ldd, uint16_t* hi, uint16_t* lo) {
   // dst row i is column i of src: dst[i*ldd + k] = src[k + i*lds]
   const long n = (long)rows * cols;
   if (n <= 0) return;
   copy_rows_f64_to_f32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rows, cols, src, lds,
-                                                                        dst, ldd);
+                                                                        dst, ldd, hi, lo);
   L1_HIP(hipGetLastError());
 }
 

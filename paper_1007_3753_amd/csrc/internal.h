@@ -62,9 +62,10 @@ double power_lambda_max64(hipStream_t s, int n, const double* M, int ldm, double
 // written as FP32, and optionally as a BF16 hi/lo split.
 void to_rowmajor_f32(hipStream_t s, int rows, int cols, const double* src, int lds,
                      float* dst, int ldd, uint16_t* hi, uint16_t* lo);
-// dst[i*ldd + k] = src[k + i*lds]: a plain FP32 copy of the transpose.
+// dst[i*ldd + k] = src[k + i*lds]: the transpose in FP32, and optionally as
+// a BF16 hi/lo split.
 void transpose_f64_to_f32(hipStream_t s, int rows, int cols, const double* src, int lds,
-                          float* dst, int ldd);
+                          float* dst, int ldd, uint16_t* hi = nullptr, uint16_t* lo = nullptr);
 
 // FP64 optimality report, one workgroup per instance.
 void kkt64(hipStream_t s, int problem, int m, int nd, int split, const float* A, int lda,
@@ -160,7 +161,25 @@ struct GemmArgs {
   const float* eps;            // P_{1,2} radii (the ball scale comes from prev_partial)
   const float* wcap2;          // squared L1_DIVERGED thresholds per column (null: none)
   const float* dscale2;        // (beta0 / beta)^2 per column (null: 1)
-  long long* stat;             // [3 + prec] += live columns, [prec] += column tiles
+  long long* stat;             // [3 + prec] += live columns, [prec] += column tiles,
+                               // [6] += live columns of structured-form launches
+  // ---- structured DALM form (cross-and-bouquet): the iteration is two
+  // launches.  The first multiplies u by the first rows of P and also writes
+  // q = u - (P u) for its rows below q_rows (0 at and beyond them); the
+  // second multiplies q by B and adds the current operand u (add_u).
+  int row_off;            // state row of the launch's output row 0 (a multiple of TILE)
+  int ptiles;             // row tiles of partial sums the test adds (0: M / TILE)
+  int test_passive;       // 1: decide like the first launch, record nothing
+  int add_u;              // DALM epilogue: v = acc + u + c (u from Ucur*, the current operand)
+  const float* Ucur;
+  const uint16_t* Ucur_hi;
+  const uint16_t* Ucur_lo;
+  float* Tq;              // q out (column-major, leading dimension ldt), FP32 ...
+  uint16_t* Tq_hi;        // ... and its BF16 hi / lo split
+  uint16_t* Tq_lo;
+  int q_rows;             // rows < q_rows carry q (0: no q output)
+  int ldt;                // leading dimension of T; > 0 marks a structured-form launch
+  int prec_mask;          // bit p set: the launch runs the tiles of arithmetic p (0: all)
 };
 
 // The alignment l1 problem of Sec. II-B (csrc/align.hip): per instance its

@@ -271,6 +271,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   // column tile run side by side and share the B tile in L2.
   const int L = blockIdx.x, xcd = L & 7, j = L >> 3;
   const int RT = a.M / 64;
+  // row tiles of partial sums the test adds (all of the iteration's, also
+  // when it is split over two launches), and this launch's first one
+  const int RTP = a.ptiles > 0 ? a.ptiles : RT, pt0 = a.row_off / 64;
   const int r_lo = (xcd * RT) / 8, r_hi = ((xcd + 1) * RT) / 8, nr = r_hi - r_lo;
   if (nr <= 0) return;
   const int ks = (EPI == EPI_PARTIAL) ? a.ksplit : 1;
@@ -287,6 +290,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     prec = a.prec;
   }
   if (slot0 >= nslots) return;  // uniform for the workgroup
+  if (a.prec_mask && !((a.prec_mask >> prec) & 1)) return;
   const int tid = threadIdx.x;
   __shared__ float s_zsc[64];
   __shared__ int s_live;
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     gfl = (a.dscale2 ? a.dscale2 : pp)[2 * cc + 1];
 #pragma unroll
     for (int i = 0; i < TEST_PRE; ++i) {
-      const int t = min(tpart + 4 * i, RT - 1);
+      const int t = min(tpart + 4 * i, RTP - 1);
 #pragma unroll
       for (int q = 0; q < NPART; ++q) tv[i][q] = pp[(long)(t * NPART + q) * a.ldp + cc];
     }
@@ -351,7 +355,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       const long cb = (long)(cc >= 0 ? cc : 0) * a.lds;   // idle slots read column 0, never stored
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        const long idx = cb + i0 + wm * 32 + bi * 16 + 4 * q;
+        const long idx = cb + a.row_off + i0 + wm * 32 + bi * 16 + 4 * q;
         pre_c[bi][bj] = *reinterpret_cast<const f4*>(a.C + idx);
         pre_w[bi][bj] = *reinterpret_cast<const f4*>(a.W + idx);
         pre_v[bi][bj] = *reinterpret_cast<const f4*>(a.V + idx);
@@ -422,11 +426,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     if (tload && live0) {
 #pragma unroll
       for (int i = 0; i < TEST_PRE; ++i)
-        if (tpart + 4 * i < RT) {
+        if (tpart + 4 * i < RTP) {
 #pragma unroll
           for (int q = 0; q < NPART; ++q) sm[q] += tv[i][q];
         }
-      for (int t = tpart + 4 * TEST_PRE; t < RT; t += 4) {
+      for (int t = tpart + 4 * TEST_PRE; t < RTP; t += 4) {
         const float* pt = a.prev_partial + (long)t * NPART * a.ldp + tcol;
 #pragma unroll
         for (int q = 0; q < NPART; ++q) sm[q] += pt[(long)q * a.ldp];
@@ -467,7 +471,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       } else {
         colidx[tsl] = -1;
       }
-      if (rt == 0) {
+      if (rt == 0 && !a.test_passive) {
         a.state_out[tcol] = st;
         if (a.arith_out && st < NPHASE) a.arith_out[tcol] = prec;
         if (live0) {
@@ -481,9 +485,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     }
     __syncthreads();
     if (s_live == 0) return;  // every column of the tile has finished
-    if (rt == 0 && tid == 0 && a.stat) {
+    if (rt == 0 && tid == 0 && a.stat && !a.test_passive) {
       atomicAdd((unsigned long long*)&a.stat[3 + prec], (unsigned long long)s_live);
       atomicAdd((unsigned long long*)&a.stat[prec], 1ull);
+      if (a.ldt > 0) atomicAdd((unsigned long long*)&a.stat[6], (unsigned long long)s_live);
     }
   }
 
@@ -493,6 +498,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   // accumulator (bi, bj), register r: row i0 + wm*32 + bi*16 + 4q + r,
   // column slot wn*32 + bj*16 + li
   if (EPI == EPI_STORE) {
+    if (a.Tq_hi && prec != PREC_F32) {
+      // the first product of the dense structured form: t in the BF16 hi /
+      // lo split the second product of a BF16 tile reads (all rows)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int col = colidx[wn * 32 + bj * 16 + li];
+        if (col < 0) continue;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+          us4 h, l;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint16_t hb = f2bf(acc[bi][bj][r]);
+            h[r] = hb;
+            l[r] = f2bf(acc[bi][bj][r] - bf2f(hb));
+          }
+          const long tix = (long)col * a.ldo + i0 + wm * 32 + bi * 16 + 4 * q;
+          *reinterpret_cast<us4*>(a.Tq_hi + tix) = h;
+          *reinterpret_cast<us4*>(a.Tq_lo + tix) = l;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       const int col = colidx[wn * 32 + bj * 16 + li];
@@ -521,8 +549,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     if (col < 0) continue;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
-      const int row0 = i0 + wm * 32 + bi * 16 + 4 * q;
-      const long idx = (long)col * a.lds + row0;
+      const int row0 = i0 + wm * 32 + bi * 16 + 4 * q;   // output row
+      const int srow = a.row_off + row0;                  // state row
+      const long idx = (long)col * a.lds + srow;
       const f4 c4 = EPI == EPI_DALM ? pre_c[bi][bj] : *reinterpret_cast<const f4*>(a.C + idx);
       const f4 wo = EPI == EPI_DALM ? pre_w[bi][bj] : *reinterpret_cast<const f4*>(a.W + idx);
       f4 wn4, un4;
@@ -559,14 +588,47 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         const float zsc = s_zsc[wn * 32 + bj * 16 + li];
         const f4 vo = pre_v[bi][bj];
         const f4 wr4 = pre_r[bi][bj];
+        // structured form: the operand the product multiplied, in the
+        // tile's arithmetic (BF16: hi; split: hi + lo; FP32: u)
+        f4 ut = {0.f, 0.f, 0.f, 0.f};
+        if (a.add_u || a.q_rows > 0) {
+          if (prec == PREC_F32 || !a.Ucur_hi) {
+            ut = *reinterpret_cast<const f4*>(a.Ucur + idx);
+          } else {
+            const us4 h = *reinterpret_cast<const us4*>(a.Ucur_hi + idx);
+            const us4 l = *reinterpret_cast<const us4*>(a.Ucur_lo + idx);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ut[r] = bf2f(h[r]) + (prec == PREC_BF16X3 ? bf2f(l[r]) : 0.0f);
+          }
+        }
+        if (a.q_rows > 0) {
+          // q = u - (P u) on the first rows (K^{-1} (u_x - B^T u_e)), 0 below
+          f4 q4;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) q4[r] = (srow + r < a.q_rows) ? ut[r] - acc[bi][bj][r] : 0.0f;
+          const long tix = (long)col * a.ldt + row0;
+          if (prec == PREC_F32 || !a.Tq_hi) {
+            *reinterpret_cast<f4*>(a.Tq + tix) = q4;
+          } else {
+            us4 h, l;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const uint16_t hb = f2bf(q4[r]);
+              h[r] = hb;
+              l[r] = f2bf(q4[r] - bf2f(hb));
+            }
+            *reinterpret_cast<us4*>(a.Tq_hi + tix) = h;
+            *reinterpret_cast<us4*>(a.Tq_lo + tix) = l;
+          }
+        }
         f4 vn4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = row0 + r;
+          const int row = srow + r;
           const bool ball = row >= a.e0;   // eps-ball block of the P_{1,2} splitting
           const float s = vo[r] + wo[r] * ib;
           const float z = ball ? s * zsc : clamp1(s);
-          const float vn = acc[bi][bj][r] + c4[r];
+          const float vn = acc[bi][bj][r] + c4[r] + (a.add_u ? ut[r] : 0.0f);
           const float wn = wo[r] - bt * (z - vn);
           const float s2 = vn + wn * ib;
           const float z2 = ball ? s2 : clamp1(s2);  // ball rows: scaled after the column norm
@@ -654,7 +716,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     if (col >= 0) {
 #pragma unroll
       for (int p = 0; p < NPART; ++p)
-        a.partial[(long)(rt * NPART + p) * a.ldp + col] = red[0][tid][p] + red[1][tid][p];
+        a.partial[(long)((rt + pt0) * NPART + p) * a.ldp + col] = red[0][tid][p] + red[1][tid][p];
     }
   }
 }

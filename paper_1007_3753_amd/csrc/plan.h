@@ -24,6 +24,22 @@ struct Plan {
   uint16_t* Plo = nullptr;
   float* Cop = nullptr;   // n_pad x m_pad
   float* Yop = nullptr;   // m_pad x n_pad (dense only)
+  // structured iteration forms (st_ok: 0 none, 1 cross-and-bouquet, 2 dense)
+  //  1: Bq = B row-major (rows K-contiguous, m_pad + TILE rows, zero padded),
+  //     T holds q = K^{-1} (u_x - B^T u_e) per column (ldt = nd_pad); R1 =
+  //     rows of the first launch
+  //  2: Rop = (A A^T + shift I)^{-1} A (m_pad x n_pad) and Bq = A^T (n_pad x
+  //     m_pad), both rows K-contiguous; T holds t = Rop u (ldt = m_pad)
+  int st_ok = 0, R1 = 0, ldt = 0;
+  float* Bq32 = nullptr;
+  uint16_t* Bqhi = nullptr;
+  uint16_t* Bqlo = nullptr;
+  float* R32 = nullptr;
+  uint16_t* Rhi = nullptr;
+  uint16_t* Rlo = nullptr;
+  float* Tf = nullptr;
+  uint16_t* Th = nullptr;
+  uint16_t* Tl = nullptr;
   // PALM operators
   float* M32 = nullptr;   // nd_pad x nd_pad
   uint16_t* Mhi = nullptr;

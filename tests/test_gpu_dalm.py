@@ -48,16 +48,20 @@ def test_dense_fixed_iterations_match_oracle(k):
     assert np.all(_np(r.iters) == k) and np.all(_np(r.status) == 0)
 
 
+@pytest.mark.parametrize("form", ["dense", "structured"])
 @pytest.mark.parametrize("k,r", [(1, 5e-5), (5, 5e-5), (60, 2e-4)])
-def test_cab_fixed_iterations_match_oracle(k, r):
+def test_cab_fixed_iterations_match_oracle(k, r, form):
     # 130 rows / 49 columns: several tiles with ragged edges in both dimensions.
     # Per-element bound r (x column rms): FP32 products (unit 6e-8) over
     # ~200-term sums, growing with the iterations; with the face-shaped
     # default penalty beta0/8 the operand before the first refresh is
     # O(||w||/beta), eight times that of beta0, whose rounding the later
-    # iterations carry (2e-4 at 60 iterations)
+    # iterations carry (2e-4 at 60 iterations).  The structured form (the x
+    # rows of P u, q = u_x - (P u)_x, then u_e + B q; the x block ends inside
+    # the first row tile, so that tile's e rows come from P u) runs the same
+    # Algorithm 2 steps with other rounding.
     P = cab_problem(m=130, classes=7, per_class=7, N=70, cfg=201)
-    pl = _plan(P.A, structure="cab", max_batch=70)
+    pl = _plan(P.A, structure="cab", max_batch=70, iteration_form=form)
     r_ = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
     o = oracle_dalm(P.A, P.b[:, :6], structure="cab", fixed_iters=k)
     w = np.vstack([_np(r_.x), _np(r_.e)])[:, :6]
@@ -95,6 +99,69 @@ def test_cab_converged_matches_lp(precision, bound):
         assert_solution_close(x, w_lp[:P.n_dict], bound, what=f"x of instance {j}")
     rep = pl.kkt(b, r.x, e=r.e, y=r.y).cpu().numpy()
     assert rep[:, 0].max() < 1e-5 and rep[:, 3].max() < 1e-4
+
+
+@pytest.mark.parametrize("precision,bound", [("fp32", 1e-4), ("bf16_refine", 1e-4)])
+def test_structured_form_converges_to_the_lp_optimum(precision, bound):
+    # the structured iteration (forced on a batch the automatic rule would
+    # run densely): converged, within the bound of the exact LP optimum, and
+    # the solve reports its instance-iterations as structured, but for the
+    # last few instances' iterations, which the tail kernel runs densely, and
+    # the split-BF16 phase of BF16 + refinement, which stays dense
+    P = cab_problem(m=300, classes=20, per_class=7, N=96, frac=0.3, cfg=202)
+    pl = _plan(P.A, structure="cab", precision=precision, max_batch=96, iteration_form="structured")
+    b = torch.as_tensor(P.b, device="cuda")
+    r = pl.solve(b, tol=4e-6, max_iter=30000)
+    st = pl.last_stats()
+    assert np.all(_np(r.status) == 0), np.unique(_np(r.status), return_counts=True)
+    assert 0.9 * (st["cols_fp32"] + st["cols_bf16"]) < st["cols_structured"] <= st["cols_fp32"] + st["cols_bf16"]
+    Af = full_matrix(P.A, "cab")
+    for j in (0, 37, 95):
+        w_lp, _ = p1_lp(Af, P.b[:, j])
+        assert_solution_close(_np(r.x)[:, j], w_lp[:P.n_dict], bound, what=f"x of instance {j}")
+        assert_solution_close(np.concatenate([_np(r.x)[:, j], _np(r.e)[:, j]]), w_lp, bound,
+                              what=f"w of instance {j}")
+    # the automatic rule keeps this batch (2 column tiles) on the dense operator
+    pa = _plan(P.A, structure="cab", precision=precision, max_batch=96)
+    pa.solve(b, tol=4e-6, max_iter=30000)
+    assert pa.last_stats()["cols_structured"] == 0
+
+
+@pytest.mark.parametrize("problem", ["p1", "qp"])
+@pytest.mark.parametrize("k,r", [(1, 5e-5), (5, 5e-5), (40, 2e-4)])
+def test_dense_structured_form_matches_oracle(problem, k, r):
+    # Gaussian 100 x 400 (m < n_dict, so t = (A A^T + shift I)^{-1} A u then
+    # v = A^T t + c): Algorithm 2's iterates, element by element, forced
+    # structured and in the automatic mode (dense for a batch of one tile)
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((100, 400))
+    A = (A / np.linalg.norm(A, axis=0)).astype(np.float32).astype(np.float64)
+    x0 = np.zeros((400, 5))
+    for j in range(5):
+        x0[rng.choice(400, 15, replace=False), j] = rng.uniform(-1, 1, 15)
+    b = (A @ x0).astype(np.float32).astype(np.float64)
+    kw = dict(problem="qp", lam=1e-2, beta=0.5) if problem == "qp" else {}
+    o = oracle_dalm(A, b, fixed_iters=k, **({"problem": "qp", "lam": 1e-2, "beta": 0.5} if problem == "qp" else {}))
+    for form in ("structured", "auto"):
+        pl = _plan(A.astype(np.float32), max_batch=5, iteration_form=form, **kw)
+        res = pl.solve(torch.as_tensor(b.astype(np.float32), device="cuda"), max_iter=-k)
+        assert (pl.last_stats()["cols_structured"] > 0) == (form == "structured")
+        assert_cols_close(_np(res.x), o.w, r, what=f"x ({form})")
+
+
+def test_structured_and_dense_forms_agree():
+    # FP32, 150 fixed iterations on 70 instances: the two forms differ only in
+    # rounding (per-element bound 2e-4 of the column rms, as for the oracle
+    # comparison at 60 iterations)
+    P = cab_problem(m=130, classes=7, per_class=7, N=70, cfg=201)
+    b = torch.as_tensor(P.b, device="cuda")
+    out = {}
+    for form in ("dense", "structured"):
+        pl = _plan(P.A, structure="cab", max_batch=70, iteration_form=form)
+        r = pl.solve(b, max_iter=-150)
+        out[form] = np.vstack([_np(r.x), _np(r.e)])
+        assert (pl.last_stats()["cols_structured"] > 0) == (form == "structured")
+    assert_cols_close(out["structured"], out["dense"], 2e-4, what="w")
 
 
 def test_batched_equals_single_instance():

@@ -69,8 +69,8 @@ def _c4_golden():
     return np.load(path)
 
 
-@pytest.mark.parametrize("precision", ["bf16_refine", "fp32"])
-def test_cab_4800x2100_golden_instances(precision):
+@pytest.mark.parametrize("precision,form", [("bf16_refine", "auto"), ("fp32", "auto")])
+def test_cab_4800x2100_golden_instances(precision, form):
     # the exact LP optima (oracle, certified) of 8 instances of the 4800 x 2100
     # workload -- the five most corrupted (~50 %), two at 35 %, one at 10 % --
     # solved in one batch, every instance converged and within 1e-4
@@ -78,7 +78,7 @@ def test_cab_4800x2100_golden_instances(precision):
     idx = [int(j) for j in g["idx"]]
     B = cab_dictionary(4800, 300, 7, cfg=4)
     b = np.concatenate([cab_instances(B, 1, 7, frac="uneven", cfg=4, first=j)[0] for j in idx], axis=1)
-    pl = _plan(B, structure="cab", precision=precision, max_batch=len(idx))
+    pl = _plan(B, structure="cab", precision=precision, max_batch=len(idx), iteration_form=form)
     r = pl.solve(torch.as_tensor(b, device="cuda"), tol=4e-6, max_iter=40000)
     st = _np(r.status)
     assert np.all(st == 0), (st, _np(r.iters))
@@ -104,8 +104,13 @@ def test_cab_4800x2100_n2048(precision):
     t = time.time()
     r = pl.solve(b, tol=4e-6, max_iter=40000)
     st = _np(r.status)
+    sts = pl.last_stats()
     print(f"4800 x 2100, 2048 instances ({precision}): {time.time() - t:.1f} s, status {np.bincount(st.astype(int), minlength=4)}, "
-          f"iterations max {int(_np(r.iters).max())}", flush=True)
+          f"iterations max {int(_np(r.iters).max())}, structured share "
+          f"{sts['cols_structured'] / max(sts['cols_fp32'] + sts['cols_bf16'] + sts['cols_split'], 1):.2f}", flush=True)
+    # the automatic rule runs FP32 plans in the structured form while 16 or
+    # more column tiles are active, BF16 + refinement on the dense operator
+    assert (sts["cols_structured"] > 0) == (precision == "fp32")
     assert np.all(st == 0), np.bincount(st.astype(int))
     X = _np(r.x)
     err = rel_err_cols(X, P.x0)
