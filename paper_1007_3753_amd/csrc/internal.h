@@ -180,6 +180,7 @@ struct GemmArgs {
   int q_rows;             // rows < q_rows carry q (0: no q output)
   int ldt;                // leading dimension of T; > 0 marks a structured-form launch
   int prec_mask;          // bit p set: the launch runs the tiles of arithmetic p (0: all)
+  int fam;                // 1: every tile is BF16 or split BF16 (the lighter kernel instance)
 };
 
 // The alignment l1 problem of Sec. II-B (csrc/align.hip): per instance its

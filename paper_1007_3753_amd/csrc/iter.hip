@@ -258,8 +258,14 @@ __device__ inline void mainloop_bf16(const GemmArgs& a, int i0, const int* colid
 #undef L1_FETCH_BF
 }
 
-template <int EPI>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
+// FAM = 1: the BF16-family instantiation (BF16 and split-BF16 tiles only,
+// the epilogue's loads after the K loop, fewer test loads ahead of it), held
+// to 256 registers so that two workgroups share a compute unit: on batches
+// with more column tiles than compute units one workgroup's K loop then
+// covers the other's memory waits.
+template <int EPI, int FAM = 0>
+__global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a) {
+  constexpr int TP = FAM == 1 ? 4 : TEST_PRE;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];   // GEMM_LDS bytes
   __shared__ int colidx[64];
   __shared__ float red[2][64][NPART];
@@ -315,7 +321,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   const bool tload = test && tcol >= 0 && a.prev_partial != nullptr;
   int st0 = NPHASE, ar0 = 0;
   float wcap = INFINITY, dsc = 1.0f, gfl = 0.0f;
-  float tv[TEST_PRE][NPART];
+  float tv[TP][NPART];
   if (test) {
     // unconditional loads from clamped addresses (values masked when
     // summed); an absent per-instance array reads a stand-in (the partial
@@ -329,7 +335,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     dsc = (a.dscale2 ? a.dscale2 : pp)[2 * cc];
     gfl = (a.dscale2 ? a.dscale2 : pp)[2 * cc + 1];
 #pragma unroll
-    for (int i = 0; i < TEST_PRE; ++i) {
+    for (int i = 0; i < TP; ++i) {
       const int t = min(tpart + 4 * i, RTP - 1);
 #pragma unroll
       for (int q = 0; q < NPART; ++q) tv[i][q] = pp[(long)(t * NPART + q) * a.ldp + cc];
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   // 1200 x 700 cross-and-bouquet batch of 512: epilogue 5.6 -> 3.9 us per
   // launch); the K loop's waits cover them, being younger
   f4 pre_c[2][2], pre_w[2][2], pre_v[2][2], pre_r[2][2];
-  if (EPI == EPI_DALM) {
+  if (EPI == EPI_DALM && FAM == 0) {
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
 #pragma unroll
@@ -383,8 +389,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       // slices in flight per arithmetic, from a sweep of 2..8 on the
       // 1200 x 700 cross-and-bouquet operator (deeper split-BF16 prefetch
       // makes the compiler serialise the loads)
-      if (prec == PREC_F32 || (EPI == EPI_REFRESH)) mainloop_f32<8>(a, i0, colidx, lds, acc, kb, ke);
-      else if (prec == PREC_BF16X3) mainloop_bf16<true, 3>(a, i0, colidx, lds, acc, kb, ke);
+      if (FAM == 0 && (prec == PREC_F32 || (EPI == EPI_REFRESH))) mainloop_f32<8>(a, i0, colidx, lds, acc, kb, ke);
+      else if (prec == PREC_BF16X3) mainloop_bf16<true, FAM == 1 ? 2 : 3>(a, i0, colidx, lds, acc, kb, ke);
       else mainloop_bf16<false, 4>(a, i0, colidx, lds, acc, kb, ke);
     }
     if (EPI == EPI_PARTIAL) {
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     asm volatile("" : "+v"(dsc));
     asm volatile("" : "+v"(gfl));
 #pragma unroll
-    for (int i = 0; i < TEST_PRE; ++i)
+    for (int i = 0; i < TP; ++i)
 #pragma unroll
       for (int q = 0; q < NPART; ++q) asm volatile("" : "+v"(tv[i][q]));
     if (!a.arith_in) ar0 = NPHASE;
@@ -425,12 +431,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     const bool live0 = tcol >= 0 && st0 < NPHASE;
     if (tload && live0) {
 #pragma unroll
-      for (int i = 0; i < TEST_PRE; ++i)
+      for (int i = 0; i < TP; ++i)
         if (tpart + 4 * i < RTP) {
 #pragma unroll
           for (int q = 0; q < NPART; ++q) sm[q] += tv[i][q];
         }
-      for (int t = tpart + 4 * TEST_PRE; t < RTP; t += 4) {
+      for (int t = tpart + 4 * TP; t < RTP; t += 4) {
         const float* pt = a.prev_partial + (long)t * NPART * a.ldp + tcol;
 #pragma unroll
         for (int q = 0; q < NPART; ++q) sm[q] += pt[(long)q * a.ldp];
@@ -552,8 +558,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       const int row0 = i0 + wm * 32 + bi * 16 + 4 * q;   // output row
       const int srow = a.row_off + row0;                  // state row
       const long idx = (long)col * a.lds + srow;
-      const f4 c4 = EPI == EPI_DALM ? pre_c[bi][bj] : *reinterpret_cast<const f4*>(a.C + idx);
-      const f4 wo = EPI == EPI_DALM ? pre_w[bi][bj] : *reinterpret_cast<const f4*>(a.W + idx);
+      const bool pre = EPI == EPI_DALM && FAM == 0;
+      const f4 c4 = pre ? pre_c[bi][bj] : *reinterpret_cast<const f4*>(a.C + idx);
+      const f4 wo = pre ? pre_w[bi][bj] : *reinterpret_cast<const f4*>(a.W + idx);
       f4 wn4, un4;
       if (EPI == EPI_REFRESH) {
         // w_ref = w, c_ref = (C0 - P w) / beta, and the next operand
@@ -586,8 +593,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         const float bt = a.beta[col];
         const float ib = 1.0f / bt;
         const float zsc = s_zsc[wn * 32 + bj * 16 + li];
-        const f4 vo = pre_v[bi][bj];
-        const f4 wr4 = pre_r[bi][bj];
+        const f4 vo = pre ? pre_v[bi][bj] : *reinterpret_cast<const f4*>(a.V + idx);
+        const f4 wr4 = pre ? pre_r[bi][bj]
+                           : (a.Wref ? *reinterpret_cast<const f4*>(a.Wref + idx) : f4{0.f, 0.f, 0.f, 0.f});
         // structured form: the operand the product multiplied, in the
         // tile's arithmetic (BF16: hi; split: hi + lo; FP32: u)
         f4 ut = {0.f, 0.f, 0.f, 0.f};
@@ -737,13 +745,18 @@ void launch_gemm(hipStream_t s, int epi, const GemmArgs& a0, int n_col_tiles) {
                           reinterpret_cast<const void*>(gemm_kernel<EPI_DALM>),
                           reinterpret_cast<const void*>(gemm_kernel<EPI_FISTA>),
                           reinterpret_cast<const void*>(gemm_kernel<EPI_PARTIAL>),
-                          reinterpret_cast<const void*>(gemm_kernel<EPI_REFRESH>)})
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_REFRESH>),
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_DALM, 1>),
+                          reinterpret_cast<const void*>(gemm_kernel<EPI_PARTIAL, 1>)})
       ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LDS) ==
                      hipSuccess;
     return ok;
   }();
   L1_REQUIRE(lds_ok, "cannot give the iteration GEMM its LDS stages");
-  if (epi == EPI_STORE) gemm_kernel<EPI_STORE><<<grid, 256, GEMM_LDS, s>>>(a);
+  const bool fam1 = a.fam == 1 && (epi == EPI_DALM || epi == EPI_PARTIAL);
+  if (fam1 && epi == EPI_DALM) gemm_kernel<EPI_DALM, 1><<<grid, 256, GEMM_LDS, s>>>(a);
+  else if (fam1) gemm_kernel<EPI_PARTIAL, 1><<<grid, 256, GEMM_LDS, s>>>(a);
+  else if (epi == EPI_STORE) gemm_kernel<EPI_STORE><<<grid, 256, GEMM_LDS, s>>>(a);
   else if (epi == EPI_DALM) gemm_kernel<EPI_DALM><<<grid, 256, GEMM_LDS, s>>>(a);
   else if (epi == EPI_FISTA) gemm_kernel<EPI_FISTA><<<grid, 256, GEMM_LDS, s>>>(a);
   else if (epi == EPI_REFRESH) gemm_kernel<EPI_REFRESH><<<grid, 256, GEMM_LDS, s>>>(a);

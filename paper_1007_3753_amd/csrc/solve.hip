@@ -259,6 +259,8 @@ void solve_dalm(Plan* p, const SolveArgs& a) {
   it.Wref = p->Wref;
   it.stat = p->stat;
   it.ws = p->ws;
+  // BF16 plans never run an FP32 iteration tile (the refresh is its own launch)
+  it.fam = (p->d.precision != L1_FP32) ? 1 : 0;
   DalmCheck ck{};
   ck.N = N;
   ck.ldp = p->N_pad;
