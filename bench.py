@@ -128,6 +128,10 @@ ALIGN_WORKLOADS = {
 # columns, 200 +-1 spikes, noise 0.01, lambda = 1e-3, 64 instances sharing A;
 # batched against one instance per launch.
 QP_WORKLOADS = {"qp-2000x8000-n64": dict(tol=3e-6, max_iter=30000, plain=2)}
+# Plain single-instance (P1): Gaussian 200 x 1000 with unit columns, 20 N(0,1)
+# nonzeros at random positions, b = A x0, one instance per solve, FP32,
+# stopping at relative change 1e-6 (Sec. VI-A shape); 8 planted x0 share A.
+PLAIN_WORKLOADS = {"plain-200x1000": dict(m=200, n=1000, k=20, N=8, tol=1e-6, max_iter=20000)}
 # The differentiable unrolled DALM: the 1200 x 700 cross-and-bouquet
 # dictionary, 256 corrupted test vectors, 50 iterations, checkpoints every 10,
 # forward and backward to b and B.
@@ -144,7 +148,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS) + sorted(E1_WORKLOADS) + sorted(ALIGN_WORKLOADS)
-                    + sorted(QP_WORKLOADS) + sorted(UNROLLED_WORKLOADS))
+                    + sorted(QP_WORKLOADS) + sorted(UNROLLED_WORKLOADS) + sorted(PLAIN_WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16_refine", "bf16x3"],
                     help="default: bf16_refine for the cross-and-bouquet workloads, fp32 for e1-*")
     ap.add_argument("--form", default="auto", choices=["auto", "dense", "structured"],
@@ -205,6 +209,8 @@ def main():
         return qp_main(args)
     if args.workload in UNROLLED_WORKLOADS:
         return unrolled_main(args)
+    if args.workload in PLAIN_WORKLOADS:
+        return plain_main(args)
     if args.precision is None:
         args.precision = WORKLOADS[args.workload]["precision"]
     if args.method != "dalm":
@@ -441,6 +447,115 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = x.numel() * 4
 
+    print(json.dumps(out), flush=True)
+
+
+def plain_main(args):
+    """One instance per solve: the plain path of (P1) by DALM or PALM in FP32
+    on the 200 x 1000 Gaussian workload.  A step solves the 8 instances one
+    after another (each to relative change 1e-6); accuracy against the exact
+    LP optimum of each instance; the FP64 oracle on the same instances is the
+    CPU baseline."""
+    import numpy as np
+    import torch
+
+    from paper_1007_3753_amd import Plan
+    from workloads import dense_p1
+    from oracle import p1_lp
+
+    wl = PLAIN_WORKLOADS[args.workload]
+    method = args.method if args.method in ("dalm", "palm") else "dalm"
+    P = dense_p1(m=wl["m"], n=wl["n"], k=wl["k"], N=wl["N"])
+    dev = torch.device("cuda:0")
+    A = torch.as_tensor(P.A, device=dev)
+    b = torch.as_tensor(P.b, device=dev)
+    N, m, n = wl["N"], wl["m"], wl["n"]
+    plan = Plan(A, method=method, precision="fp32", max_batch=1, time_kernels=True)
+    plan_ms = plan.last_stats()["plan_ms"]
+
+    def step():
+        out = []
+        for j in range(N):
+            out.append(plan.solve(b[:, j:j + 1], tol=wl["tol"], max_iter=wl["max_iter"]))
+        return out
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    kern_ms, iters_tot, launches = 0.0, 0, 0.0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rs = step()
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N / (ms_per_step / 1e3)
+    # per-iteration kernel time of the last instance's solve (HIP events)
+    st = plan.last_stats()
+    X = np.stack([r.x.cpu().numpy()[:, 0].astype(np.float64) for r in rs], axis=1)
+    its = [int(r.iters[0]) for r in rs]
+    sts = [int(r.status[0]) for r in rs]
+    errs = []
+    for j in range(N):
+        x_lp, _ = p1_lp(P.A, P.b[:, j])
+        errs.append(float(np.linalg.norm(X[:, j] - x_lp) / np.linalg.norm(x_lp)))
+    out = {
+        "metric": f"solves/sec at rel. err <=1e-4 vs FP64 oracle (plain single-instance {method.upper()})",
+        "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (the paper's noise-free Gaussian recipe with N(0,1) nonzeros, seeded)",
+        "config": {"workload": args.workload, "m": m, "n": n, "d": wl["k"], "N": 1, "instances_per_step": N,
+                   "problem": "P1", "structure": "dense", "method": method, "precision": "fp32",
+                   "tol": wl["tol"]},
+        "plan_ms": round(plan_ms, 2),
+        "iterations": its, "status": sts,
+        "rel_err_vs_lp": {"max": max(errs), "all": errs},
+    }
+    if method == "dalm" and st["timed_launches"] > 0:
+        # HBM roofline of the iteration launch (N = 1): the method's own bytes,
+        # the dictionary twice and the FP32 factor (both solves) plus the state
+        wm = dalm_work_model(m, n, "dense")
+        per_launch = wm["matrix"](4) + wm["state"]
+        us = 1e3 * st["timed_ms"] / st["timed_launches"]
+        ach = per_launch / (us * 1e-6) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(ach / PEAK_HBM_GBS, 4), "avg_launch_us": round(us, 3),
+                           "launches_timed": int(st["timed_launches"]),
+                           "algorithmic_bytes_per_launch": round(per_launch), "traffic": None,
+                           "kernel": "DALM iteration: gemm_kernel<EPI_DALM> of one instance (with its split-K "
+                                     "part), HIP events around the blocks of the last solve"}
+    elif method == "palm":
+        # wall clock per FISTA step of the last solve: the Gram matrix (n x n
+        # FP32) once + per instance n * 24 bytes
+        inner = max(st["inner_iterations"], 1.0)
+        us = 1e3 * st["solve_ms"] / inner
+        per_launch = 4.0 * n * n + 24.0 * n
+        ach = per_launch / (us * 1e-6) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(ach / PEAK_HBM_GBS, 4), "avg_launch_us": round(us, 3),
+                           "launches_timed": int(inner), "algorithmic_bytes_per_launch": round(per_launch),
+                           "traffic": None,
+                           "kernel": "PALM FISTA step: gemm_kernel<EPI_FISTA> with the Gram matrix, wall clock of "
+                                     "the last solve over its FISTA launches (e-step and multiplier launches included)"}
+    if not args.no_cpu_baseline:
+        from oracle import dalm as oracle_dalm, palm as oracle_palm
+        t = time.perf_counter()
+        if method == "dalm":
+            o = oracle_dalm(P.A, P.b, tol=wl["tol"], max_iter=wl["max_iter"])
+        else:
+            o = oracle_palm(P.A, P.b, tol=wl["tol"], max_iter=wl["max_iter"])
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(N / dt, 3), "unit": "solves/s", "cores": int(_threads()),
+                               "kind": "oracle",
+                               "sample": f"the same {N} instances, FP64 NumPy/SciPy {method.upper()} to the same "
+                                         f"tolerance, {dt:.2f} s"}
+        log(f"CPU oracle: {N} instances in {dt:.2f} s")
+    plan.close()
+    log(f"{method} plain: {value:.1f} solves/s, rel. err vs LP max {max(errs):.2e}, iterations {its}")
     print(json.dumps(out), flush=True)
 
 
