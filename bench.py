@@ -778,7 +778,6 @@ def align_main(args):
             "value": round(N / dt, 2), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"all {N} instances, FP64 NumPy PALM, same tol; {dt:.1f} s, "
                       f"iterations mean {o.iters.mean():.2f}"}
-    plan.close()
     if args.copy_calibration:
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
