@@ -354,14 +354,14 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
   f4 pre_c[2][2], pre_w[2][2], pre_v[2][2], pre_r[2][2];
   if (EPI == EPI_DALM && FAM == 0) {
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
+    const int wm = wave & 1, wn = wave >> 1, ec = lane >> 2, eg = lane & 3;
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      const int cc = colidx[wn * 32 + bj * 16 + li];
+      const int cc = colidx[wn * 32 + bj * 16 + ec];
       const long cb = (long)(cc >= 0 ? cc : 0) * a.lds;   // idle slots read column 0, never stored
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
-        const long idx = cb + a.row_off + i0 + wm * 32 + bi * 16 + 4 * q;
+        const long idx = cb + a.row_off + i0 + wm * 32 + bi * 16 + 4 * eg;
         pre_c[bi][bj] = *reinterpret_cast<const f4*>(a.C + idx);
         pre_w[bi][bj] = *reinterpret_cast<const f4*>(a.W + idx);
         pre_v[bi][bj] = *reinterpret_cast<const f4*>(a.V + idx);
@@ -371,16 +371,17 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
   }
   {
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
+    const int wm = wave & 1, wn = wave >> 1, ec = lane >> 2, eg = lane & 3;
     if (EPI != EPI_PARTIAL && a.ws) {
-      // split-K reduction: sum the parts in a fixed order
+      // split-K reduction: sum the parts in a fixed order (stored in the
+      // epilogue's lane layout)
       for (int sp = 0; sp < a.ksplit; ++sp)
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
           for (int bj = 0; bj < 2; ++bj) {
-            const long o = ((long)sp * a.ws_slots + slot0 + wn * 32 + bj * 16 + li) * a.M +
-                           i0 + wm * 32 + bi * 16 + 4 * q;
+            const long o = ((long)sp * a.ws_slots + slot0 + wn * 32 + bj * 16 + ec) * a.M +
+                           i0 + wm * 32 + bi * 16 + 4 * eg;
             acc[bi][bj] += *reinterpret_cast<const f4*>(a.ws + o);
           }
     } else {
@@ -392,14 +393,26 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
       if (FAM == 0 && (prec == PREC_F32 || (EPI == EPI_REFRESH))) mainloop_f32<8>(a, i0, colidx, lds, acc, kb, ke);
       else if (prec == PREC_BF16X3) mainloop_bf16<true, FAM == 1 ? 2 : 3>(a, i0, colidx, lds, acc, kb, ke);
       else mainloop_bf16<false, 4>(a, i0, colidx, lds, acc, kb, ke);
+      // from the MFMA layout (lane li + 16 q: column li, rows 4q..4q+3 of a
+      // 16 x 16 block) to the epilogue's (lane 4 c + g: column c, rows
+      // 4g..4g+3), so that four consecutive lanes move 64 contiguous bytes of
+      // one column instead of 16 bytes of four columns
+      const int src = ((lane >> 2) + 16 * (lane & 3)) << 2;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[bi][bj][r] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(acc[bi][bj][r])));
     }
     if (EPI == EPI_PARTIAL) {
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          const long o = ((long)split * a.ws_slots + slot0 + wn * 32 + bj * 16 + li) * a.M +
-                         i0 + wm * 32 + bi * 16 + 4 * q;
+          const long o = ((long)split * a.ws_slots + slot0 + wn * 32 + bj * 16 + ec) * a.M +
+                         i0 + wm * 32 + bi * 16 + 4 * eg;
           *reinterpret_cast<f4*>(a.ws + o) = acc[bi][bj];
         }
       return;
@@ -499,17 +512,17 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
   }
 
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1, li = lane & 15, q = lane >> 4;
+  const int wm = wave & 1, wn = wave >> 1, ec = lane >> 2, eg = lane & 3;
   // ---- epilogue ----------------------------------------------------------
-  // accumulator (bi, bj), register r: row i0 + wm*32 + bi*16 + 4q + r,
-  // column slot wn*32 + bj*16 + li
+  // accumulator (bi, bj), register r of lane 4 c + g: row
+  // i0 + wm*32 + bi*16 + 4g + r, column slot wn*32 + bj*16 + c
   if (EPI == EPI_STORE) {
     if (a.Tq_hi && prec != PREC_F32) {
       // the first product of the dense structured form: t in the BF16 hi /
       // lo split the second product of a BF16 tile reads (all rows)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
-        const int col = colidx[wn * 32 + bj * 16 + li];
+        const int col = colidx[wn * 32 + bj * 16 + ec];
         if (col < 0) continue;
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) {
@@ -520,7 +533,7 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
             h[r] = hb;
             l[r] = f2bf(acc[bi][bj][r] - bf2f(hb));
           }
-          const long tix = (long)col * a.ldo + i0 + wm * 32 + bi * 16 + 4 * q;
+          const long tix = (long)col * a.ldo + i0 + wm * 32 + bi * 16 + 4 * eg;
           *reinterpret_cast<us4*>(a.Tq_hi + tix) = h;
           *reinterpret_cast<us4*>(a.Tq_lo + tix) = l;
         }
@@ -529,14 +542,14 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
     }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      const int col = colidx[wn * 32 + bj * 16 + li];
+      const int col = colidx[wn * 32 + bj * 16 + ec];
       if (col < 0) continue;
       const float sc = a.col_scale ? a.col_scale[col] : 1.0f;
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = i0 + wm * 32 + bi * 16 + 4 * q + r;
+          const int row = i0 + wm * 32 + bi * 16 + 4 * eg + r;
           if (row < a.m_true) a.out[(long)col * a.ldo + row] = acc[bi][bj][r] * sc;
         }
     }
@@ -551,11 +564,11 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
 
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj) {
-    const int col = colidx[wn * 32 + bj * 16 + li];
+    const int col = colidx[wn * 32 + bj * 16 + ec];
     if (col < 0) continue;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
-      const int row0 = i0 + wm * 32 + bi * 16 + 4 * q;   // output row
+      const int row0 = i0 + wm * 32 + bi * 16 + 4 * eg;   // output row
       const int srow = a.row_off + row0;                  // state row
       const long idx = (long)col * a.lds + srow;
       const bool pre = EPI == EPI_DALM && FAM == 0;
@@ -592,7 +605,7 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
       } else if (EPI == EPI_DALM) {
         const float bt = a.beta[col];
         const float ib = 1.0f / bt;
-        const float zsc = s_zsc[wn * 32 + bj * 16 + li];
+        const float zsc = s_zsc[wn * 32 + bj * 16 + ec];
         const f4 vo = pre ? pre_v[bi][bj] : *reinterpret_cast<const f4*>(a.V + idx);
         const f4 wr4 = pre ? pre_r[bi][bj]
                            : (a.Wref ? *reinterpret_cast<const f4*>(a.Wref + idx) : f4{0.f, 0.f, 0.f, 0.f});
@@ -701,22 +714,22 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
     }
   }
   if (EPI == EPI_REFRESH) return;   // the partial sums of the last iteration stay
-  // reduce the partial sums over the 4 lane groups of each column ...
+  // reduce the partial sums over the 4 lanes of each column ...
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
     for (int p = 0; p < NPART; ++p) {
       float v = part[bj][p];
-      v += __shfl_xor(v, 16);
-      v += __shfl_xor(v, 32);
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
       part[bj][p] = v;
     }
   // ... and over the two waves that share the columns, in a fixed order
-  if (q == 0) {
+  if (eg == 0) {
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-      for (int p = 0; p < NPART; ++p) red[wm][wn * 32 + bj * 16 + li][p] = part[bj][p];
+      for (int p = 0; p < NPART; ++p) red[wm][wn * 32 + bj * 16 + ec][p] = part[bj][p];
   }
   __syncthreads();
   if (tid < 64) {
