@@ -72,12 +72,18 @@ typedef enum { L1_DALM = 0, L1_PALM = 1, L1_DALM_CG1 = 2 } l1_method;
  * from FP64 once per plan.
  *   L1_FP32        FP32 MFMA products.
  *   L1_BF16_REFINE BF16 MFMA products until an instance's relative change and
- *                  gap are both <= refine_switch (where BF16 rounding stalls
- *                  them), then split-BF16 products (B = B_hi + B_lo,
+ *                  gap are both <= refine_switch, or for 2000 iterations,
+ *                  then split-BF16 products (B = B_hi + B_lo,
  *                  u = u_hi + u_lo; hi*hi + hi*lo + lo*hi with FP32
  *                  accumulation, ~16 significant bits) until convergence.
- *                  An instance can only be declared converged in the split
- *                  phase.
+ *                  With the FP32 refresh of the operand's reference point,
+ *                  BF16 iterations progress as fast as split ones until
+ *                  BF16 rounding holds the gap near 1e-4 relative, so the
+ *                  default threshold is low and the 2000-iteration bound
+ *                  usually ends the phase; problems that converge in a few
+ *                  hundred iterations hand over sooner with a larger
+ *                  refine_switch (e.g. 3e-3).  An instance can only be
+ *                  declared converged in the split phase.
  *   L1_BF16X3      split-BF16 products for every iteration.
  * PALM runs its FISTA products (with A^T A) in split BF16 under either BF16
  * mode, and its A x / A^T c products in FP32.                               */
@@ -103,7 +109,7 @@ typedef struct {
   double xi_growth;      /* PALM: xi <- xi * xi_growth after each outer step (<= 0 -> 1) */
   int max_inner;         /* PALM: cap on FISTA steps per outer step (<= 0 -> 100)     */
   double tol_inner;      /* PALM: FISTA relative-change tolerance (<= 0 -> solve tol) */
-  double refine_switch;  /* L1_BF16_REFINE: switch threshold (<= 0 -> 3e-3)           */
+  double refine_switch;  /* L1_BF16_REFINE: switch threshold (<= 0 -> 1e-4)           */
   int record_tape;       /* 1: fixed-count DALM solves keep checkpoints for backward */
   int checkpoint_every;  /* checkpoint spacing in iterations (<= 0 -> 10)            */
   int time_kernels;      /* 1: time the DALM iteration loop with HIP events on the
