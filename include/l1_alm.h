@@ -102,9 +102,10 @@ typedef struct {
   int max_batch;         /* upper bound on N for every solve with this plan (>= 1)   */
   double lambda;         /* QP_lambda weight (> 0); ignored otherwise                */
   double beta;           /* DALM penalty.  <= 0: per instance beta0 = ||b||_1 / m, and
-                            beta0 / 8 for L1_CAB (L1_FP32 plans, or batches of more
-                            than 64 instances).  Required (> 0) for DALM on
-                            QP_lambda, where it enters the factor.                   */
+                            for L1_CAB beta0 / 16 (batches of more than 64
+                            instances) or beta0 / 8 (smaller L1_FP32 batches).
+                            Required (> 0) for DALM on QP_lambda, where it
+                            enters the factor.                                       */
   double xi;             /* PALM penalty.  <= 0: per instance 2 m / ||b||_1 (Sec. V-A) */
   double xi_growth;      /* PALM: xi <- xi * xi_growth after each outer step (<= 0 -> 1) */
   int max_inner;         /* PALM: cap on FISTA steps per outer step (<= 0 -> 100)     */

@@ -115,19 +115,22 @@ struct SolveArgs {
   hipStream_t s;
 };
 
-// Default DALM penalty as a multiple of beta0 = ||b||_1 / m: 1/8 for the
-// cross-and-bouquet form, 1 for dense dictionaries.  On face-shaped problems
-// the smaller penalty reaches a given error in several times fewer
-// iterations on the slowest instances (as many on the others); on Gaussian
-// dictionaries beta0 is the faster one.  The smaller penalty enlarges the
-// operand u = z - (w - w_ref)/beta until its reference is refreshed, which
-// happens only while two or more column tiles are active: with BF16
-// products a batch of N <= 64 keeps beta0 (its split-BF16 rounding would
-// stall the stopping test).
+// Default DALM penalty as a multiple of beta0 = ||b||_1 / m, for the
+// cross-and-bouquet form: 1/16 for batches of more than 64 instances, 1/8
+// (FP32) or 1 (BF16) for smaller ones; 1 for dense dictionaries.  On
+// face-shaped problems a smaller penalty reaches a given error in several
+// times fewer iterations on the slowest instances (as many on the others;
+// swept 1/32 to 1/4 on the 1200 x 700 and 4800 x 2100 batches: 1/16 within
+// 2 % of the best on both, in every arithmetic); on Gaussian dictionaries
+// beta0 is the faster one.  The smaller penalty enlarges the operand
+// u = z - (w - w_ref)/beta until its reference is refreshed, which happens
+// only while two or more column tiles are active: a batch that fits one
+// tile stalls its stopping test at 1/16 in FP32 (measured at 4800 x 2100)
+// and at 1/8 in split BF16.
 inline float default_beta_scale(const Plan* p, int N) {
   if (p->d.structure != L1_CAB) return 1.0f;
-  if (p->d.precision != L1_FP32 && N <= TILE) return 1.0f;
-  return 0.125f;
+  if (N <= TILE) return p->d.precision != L1_FP32 ? 1.0f : 0.125f;
+  return 0.0625f;
 }
 
 // L1_DIVERGED threshold factor of the plan (desc.div_factor, default 1e6)

@@ -78,6 +78,15 @@ def assert_all_close(got, ref, rtol, atol=None, what="result"):
                 f"(bound {bound.flat[k]:.3e}; rtol {rtol:g}, atol {atol:g} x rms)")
 
 
+def oracle_pen(b, structure="cab"):
+    """The oracle's default DALM penalty of every column of b, for a solve
+    whose iterates are compared with the oracle's (the library's own
+    default for large cross-and-bouquet batches is smaller)."""
+    from oracle.dalm import default_beta
+    b = np.asarray(b, np.float64)
+    return np.array([default_beta(b[:, j], structure) for j in range(b.shape[1])], np.float32)
+
+
 def rel_err_cols(got, ref):
     """Relative l2 error of each column (the metric's per-instance figure)."""
     got, ref = _f64(got), _f64(ref)

@@ -12,7 +12,7 @@ import pytest
 from oracle import dalm as oracle_dalm, p1_lp, full_matrix, kkt_report, qp_fista
 from workloads import tiny_dense, dense_p1, cab_problem, dense_qp
 
-from _parity import assert_cols_close, assert_all_close, rel_err_cols, assert_solution_close
+from _parity import assert_cols_close, assert_all_close, rel_err_cols, assert_solution_close, oracle_pen
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -53,16 +53,17 @@ def test_dense_fixed_iterations_match_oracle(k):
 def test_cab_fixed_iterations_match_oracle(k, r, form):
     # 130 rows / 49 columns: several tiles with ragged edges in both dimensions.
     # Per-element bound r (x column rms): FP32 products (unit 6e-8) over
-    # ~200-term sums, growing with the iterations; with the face-shaped
-    # default penalty beta0/8 the operand before the first refresh is
-    # O(||w||/beta), eight times that of beta0, whose rounding the later
-    # iterations carry (2e-4 at 60 iterations).  The structured form (the x
+    # ~200-term sums, growing with the iterations; with the oracle's
+    # face-shaped penalty beta0/8 (passed to the solve) the operand before
+    # the first refresh is O(||w||/beta), eight times that of beta0, whose
+    # rounding the later iterations carry (2e-4 at 60 iterations).  The structured form (the x
     # rows of P u, q = u_x - (P u)_x, then u_e + B q; the x block ends inside
     # the first row tile, so that tile's e rows come from P u) runs the same
     # Algorithm 2 steps with other rounding.
     P = cab_problem(m=130, classes=7, per_class=7, N=70, cfg=201)
     pl = _plan(P.A, structure="cab", max_batch=70, iteration_form=form)
-    r_ = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k)
+    pen = torch.as_tensor(oracle_pen(P.b), device="cuda")
+    r_ = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-k, pen=pen)
     o = oracle_dalm(P.A, P.b[:, :6], structure="cab", fixed_iters=k)
     w = np.vstack([_np(r_.x), _np(r_.e)])[:, :6]
     assert_cols_close(w, o.w, r, what="w")
@@ -150,15 +151,16 @@ def test_dense_structured_form_matches_oracle(problem, k, r):
 
 
 def test_structured_and_dense_forms_agree():
-    # FP32, 150 fixed iterations on 70 instances: the two forms differ only in
-    # rounding (per-element bound 2e-4 of the column rms, as for the oracle
-    # comparison at 60 iterations)
+    # FP32, 150 fixed iterations on 70 instances at penalty beta0/8: the two
+    # forms differ only in rounding (per-element bound 2e-4 of the column
+    # rms, as for the oracle comparison at 60 iterations)
     P = cab_problem(m=130, classes=7, per_class=7, N=70, cfg=201)
     b = torch.as_tensor(P.b, device="cuda")
+    pen = torch.as_tensor(oracle_pen(P.b), device="cuda")
     out = {}
     for form in ("dense", "structured"):
         pl = _plan(P.A, structure="cab", max_batch=70, iteration_form=form)
-        r = pl.solve(b, max_iter=-150)
+        r = pl.solve(b, max_iter=-150, pen=pen)
         out[form] = np.vstack([_np(r.x), _np(r.e)])
         assert (pl.last_stats()["cols_structured"] > 0) == (form == "structured")
     assert_cols_close(out["structured"], out["dense"], 2e-4, what="w")

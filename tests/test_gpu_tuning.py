@@ -10,7 +10,7 @@ import pytest
 from oracle import dalm as oracle_dalm
 from workloads import cab_problem
 
-from _parity import assert_cols_close, assert_all_close, rel_err_cols
+from _parity import assert_cols_close, assert_all_close, rel_err_cols, oracle_pen
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -43,13 +43,14 @@ def test_any_table_gives_the_oracle_iterates(ks):
     P = cab_problem(m=300, classes=20, per_class=7, N=130, frac=0.3, cfg=62)
     pl = _plan(P, precision="fp32", max_batch=130)
     pl.set_ksplit([0, ks, ks, ks])
-    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-30)
+    pen = torch.as_tensor(oracle_pen(P.b), device="cuda")
+    r = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-30, pen=pen)
     cols = [0, 64, 129]
     o = oracle_dalm(P.A, P.b[:, cols], structure="cab", fixed_iters=30)
     x = r.x.cpu().numpy().astype(np.float64)[:, cols]
     assert_cols_close(x, o.w[:P.A.shape[1]], 5e-5, what="x")
     # the same table gives the same bits
-    r2 = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-30)
+    r2 = pl.solve(torch.as_tensor(P.b, device="cuda"), max_iter=-30, pen=pen)
     assert torch.equal(r.x, r2.x)
 
 
