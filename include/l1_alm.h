@@ -76,14 +76,15 @@ typedef enum { L1_DALM = 0, L1_PALM = 1, L1_DALM_CG1 = 2 } l1_method;
  *                  then split-BF16 products (B = B_hi + B_lo,
  *                  u = u_hi + u_lo; hi*hi + hi*lo + lo*hi with FP32
  *                  accumulation, ~16 significant bits) until convergence.
- *                  With the FP32 refresh of the operand's reference point,
- *                  BF16 iterations progress as fast as split ones until
- *                  BF16 rounding holds the gap near 1e-4 relative, so the
- *                  default threshold is low and the 2000-iteration bound
- *                  usually ends the phase; problems that converge in a few
- *                  hundred iterations hand over sooner with a larger
- *                  refine_switch (e.g. 3e-3).  An instance can only be
- *                  declared converged in the split phase.
+ *                  With the FP32 refresh of the operand's reference point
+ *                  (batches of more than 64 instances), BF16 iterations
+ *                  progress as fast as split ones until BF16 rounding holds
+ *                  the gap near 1e-4 relative, so the default threshold
+ *                  there is low (1e-4) and the 2000-iteration bound usually
+ *                  ends the phase; smaller batches default to 3e-3, and
+ *                  problems that converge in a few hundred iterations hand
+ *                  over sooner with a larger refine_switch.  An instance
+ *                  can only be declared converged in the split phase.
  *   L1_BF16X3      split-BF16 products for every iteration.
  * PALM runs its FISTA products (with A^T A) in split BF16 under either BF16
  * mode, and its A x / A^T c products in FP32.                               */
@@ -110,7 +111,8 @@ typedef struct {
   double xi_growth;      /* PALM: xi <- xi * xi_growth after each outer step (<= 0 -> 1) */
   int max_inner;         /* PALM: cap on FISTA steps per outer step (<= 0 -> 100)     */
   double tol_inner;      /* PALM: FISTA relative-change tolerance (<= 0 -> solve tol) */
-  double refine_switch;  /* L1_BF16_REFINE: switch threshold (<= 0 -> 1e-4)           */
+  double refine_switch;  /* L1_BF16_REFINE: switch threshold (<= 0 -> 1e-4, or 3e-3 for
+                            batches of at most 64 instances)                         */
   int record_tape;       /* 1: fixed-count DALM solves keep checkpoints for backward */
   int checkpoint_every;  /* checkpoint spacing in iterations (<= 0 -> 10)            */
   int time_kernels;      /* 1: time the DALM iteration loop with HIP events on the
