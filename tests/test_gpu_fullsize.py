@@ -122,10 +122,13 @@ def test_cab_4800x2100_n2048(precision):
     assert rep[:, 0].max() < 3e-5 and rep[:, 1].max() < 2e-3 and rep[:, 3].max() < 1e-3
 
 
-def test_qp_2000x8000_n64():
-    # Gaussian 2000 x 8000, +-1 spikes plus noise, lambda = 1e-3, 64 instances, FP32
+@pytest.mark.parametrize("beta_div", [1.0, 3.0])
+def test_qp_2000x8000_n64(beta_div):
+    # Gaussian 2000 x 8000, +-1 spikes plus noise, lambda = 1e-3, 64 instances,
+    # FP32, at the penalty beta0 = mean ||b||_1 / m and at beta0/3 (the
+    # benchmark's)
     P = dense_qp()
-    beta = float(np.mean(np.abs(P.b.astype(np.float64)).sum(0) / P.m))
+    beta = float(np.mean(np.abs(P.b.astype(np.float64)).sum(0) / P.m)) / beta_div
     pl = _plan(P.A, problem="qp", lam=P.lam, beta=beta, max_batch=P.N)
     b = torch.as_tensor(P.b, device="cuda")
     r = pl.solve(b, tol=3e-6, max_iter=30000)
