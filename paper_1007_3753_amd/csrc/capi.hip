@@ -427,9 +427,19 @@ int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N, const flo
     if (y_dev) L1_REQUIRE(ldy >= p->m, "bad ldy");
     if (e_dev) L1_REQUIRE(lde >= p->m, "bad lde");
     const int split = (p->d.structure == L1_CAB) ? 1 : 0;
-    kkt64(reinterpret_cast<hipStream_t>(stream), prob, p->m, p->nd, split, p->A, p->m, b_dev,
-          ldb, x_dev, ldx, e_dev, lde, y_dev, ldy, eps_dev, p->d.lambda, N, p->kkt_rbuf,
-          report_dev);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!p->kkt_A64) {
+      const size_t Np = (size_t)p->N_pad;
+      double* A64 = dalloc<double>((size_t)p->m * std::max(p->nd, 1), p->owned);
+      p->kkt_X = dalloc<double>((size_t)std::max(p->nd, 1) * Np, p->owned);
+      p->kkt_U = dalloc<double>((size_t)p->m * Np, p->owned);
+      p->kkt_G = dalloc<double>((size_t)std::max(p->nd, 1) * Np, p->owned);
+      to_f64(s, (long)p->m * p->nd, p->A, A64);
+      p->kkt_A64 = A64;
+    }
+    kkt64_batched(s, prob, p->m, p->nd, split, p->kkt_A64, b_dev, ldb, x_dev, ldx, e_dev, lde,
+                  y_dev, ldy, eps_dev, p->d.lambda, N, p->kkt_rbuf, p->kkt_X, p->kkt_U, p->kkt_G,
+                  report_dev);
     return L1_OK;
   } catch (const Fail& f) {
     return f.code;

@@ -509,4 +509,144 @@ void kkt64(hipStream_t s, int problem, int m, int nd, int split, const float* A,
   L1_HIP(hipGetLastError());
 }
 
+__global__ void to_f64_kernel(long n, const float* src, double* dst) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+void to_f64(hipStream_t s, long n, const float* src, double* dst) {
+  if (n <= 0) return;
+  to_f64_kernel<<<(unsigned)std::min<long>((n + 255) / 256, 8192), 256, 0, s>>>(n, src, dst);
+  L1_HIP(hipGetLastError());
+}
+
+// operands of the batched report: R = b - e (the product is subtracted
+// next), X = x and U = y in FP64
+__global__ void kkt_prep_kernel(int m, int nd, int N, const float* b, int ldb, const float* e,
+                                int lde, const float* x, int ldx, const float* y, int ldy,
+                                double* R, double* X, double* U) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < max(m, nd); i += gridDim.x * blockDim.x) {
+    if (i < m) {
+      R[i + (long)j * m] = (double)b[i + (long)j * ldb] - (e ? (double)e[i + (long)j * lde] : 0.0);
+      if (y) U[i + (long)j * m] = (double)y[i + (long)j * ldy];
+    }
+    if (i < nd) X[i + (long)j * nd] = (double)x[i + (long)j * ldx];
+  }
+}
+__global__ void kkt_scale_kernel(long n, const double* R, double c, double* U) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    U[i] = R[i] * c;
+}
+
+// the report of instance j from R (its residual) and G (A^T u); the same
+// quantities and formulas as kkt64_kernel
+__global__ __launch_bounds__(256) void kkt_report_kernel(int problem, int m, int nd, int split,
+                                                         const float* b, int ldb, const float* x,
+                                                         int ldx, const float* e, int lde,
+                                                         const float* y, int ldy, const float* eps,
+                                                         double lambda, const double* R,
+                                                         const double* G, double* report) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  const float* bj = b + (long)j * ldb;
+  const float* xj = x + (long)j * ldx;
+  const float* ej = (split && e) ? e + (long)j * lde : nullptr;
+  const float* yj = y ? y + (long)j * ldy : nullptr;
+  const double* r = R + (long)j * m;
+  const double* g = G + (long)j * nd;
+  double rr = 0.0, bb = 0.0, by = 0.0, yy = 0.0, br = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double bi = (double)bj[i];
+    rr += r[i] * r[i];
+    bb += bi * bi;
+    br += bi * r[i];
+    if (yj) {
+      by += bi * (double)yj[i];
+      yy += (double)yj[i] * (double)yj[i];
+    }
+  }
+  rr = block_sum(rr, sh);
+  bb = block_sum(bb, sh);
+  by = block_sum(by, sh);
+  yy = block_sum(yy, sh);
+  br = block_sum(br, sh);
+  double l1 = 0.0, wmax = 0.0;
+  for (int k = threadIdx.x; k < nd; k += 256) {
+    l1 += fabs((double)xj[k]);
+    wmax = fmax(wmax, fabs((double)xj[k]));
+  }
+  if (ej && problem == 0)
+    for (int i = threadIdx.x; i < m; i += 256) {
+      l1 += fabs((double)ej[i]);
+      wmax = fmax(wmax, fabs((double)ej[i]));
+    }
+  l1 = block_sum(l1, sh);
+  wmax = block_max(wmax, sh);
+  double gmax = 0.0, serr = 0.0;
+  const double thr = 1e-6 * wmax;
+  for (int k = threadIdx.x; k < nd; k += 256) {
+    gmax = fmax(gmax, fabs(g[k]));
+    const double wk = (double)xj[k];
+    if (fabs(wk) > thr && wmax > 0.0) serr = fmax(serr, fabs(g[k] - (wk > 0 ? 1.0 : -1.0)));
+  }
+  if (ej && problem == 0 && yj)
+    for (int i = threadIdx.x; i < m; i += 256) {
+      const double gi = (double)yj[i];
+      gmax = fmax(gmax, fabs(gi));
+      const double wk = (double)ej[i];
+      if (fabs(wk) > thr && wmax > 0.0) serr = fmax(serr, fabs(gi - (wk > 0 ? 1.0 : -1.0)));
+    }
+  gmax = block_max(gmax, sh);
+  serr = block_max(serr, sh);
+  if (threadIdx.x == 0) {
+    double* out = report + 4 * (long)j;
+    const double nb = fmax(sqrt(bb), 1e-300);
+    if (problem == 0) {
+      out[0] = sqrt(rr) / nb;
+      out[1] = fmax(gmax - 1.0, 0.0);
+      out[2] = serr;
+      out[3] = fabs(l1 - by) / fmax(l1, 1e-300);
+    } else if (problem == 2) {
+      // gap: primal 1/2||r||^2 + lambda||x||_1, dual b^T th - 1/2||th||^2, th = r / max(gmax,1)
+      const double sc = fmax(gmax, 1.0);
+      const double pobj = 0.5 * rr + lambda * l1;
+      const double dobj = br / sc - 0.5 * rr / (sc * sc);
+      out[0] = 0.0;
+      out[1] = fmax(gmax - 1.0, 0.0);
+      out[2] = serr;
+      out[3] = fabs(pobj - dobj) / fmax(fabs(pobj), 1e-300);
+    } else {
+      const double ep = (double)eps[j];
+      out[0] = fmax(sqrt(rr) - ep, 0.0) / nb;
+      out[1] = fmax(gmax - 1.0, 0.0);
+      out[2] = serr;
+      out[3] = fabs(l1 - (by - ep * sqrt(yy))) / fmax(l1, 1e-300);
+    }
+  }
+}
+
+void kkt64_batched(hipStream_t s, int problem, int m, int nd, int split, const double* A64,
+                   const float* b, int ldb, const float* x, int ldx, const float* e, int lde,
+                   const float* y, int ldy, const float* eps, double lambda, int N, double* R,
+                   double* X, double* U, double* G, double* report) {
+  if (N <= 0) return;
+  const float* ef = split ? e : nullptr;
+  const float* yu = (problem == 2) ? nullptr : y;
+  dim3 grid((unsigned)std::min((std::max(m, nd) + 255) / 256, 64), (unsigned)N);
+  kkt_prep_kernel<<<grid, 256, 0, s>>>(m, nd, N, b, ldb, ef, lde, x, ldx, yu, ldy, R, X, U);
+  L1_HIP(hipGetLastError());
+  if (nd > 0) gemm64(s, 'N', 'N', m, N, nd, -1.0, A64, m, X, nd, 1.0, R, m);
+  if (problem == 2) {
+    const long n = (long)m * N;
+    kkt_scale_kernel<<<(unsigned)std::min<long>((n + 255) / 256, 8192), 256, 0, s>>>(n, R, 1.0 / lambda, U);
+    L1_HIP(hipGetLastError());
+  } else if (!y) {
+    L1_HIP(hipMemsetAsync(U, 0, sizeof(double) * (size_t)m * N, s));
+  }
+  if (nd > 0) gemm64(s, 'T', 'N', nd, N, m, 1.0, A64, m, U, m, 0.0, G, nd);
+  kkt_report_kernel<<<N, 256, 0, s>>>(problem, m, nd, split, b, ldb, x, ldx, e, lde, y, ldy, eps,
+                                      lambda, R, G, report);
+  L1_HIP(hipGetLastError());
+}
+
 }  // namespace l1

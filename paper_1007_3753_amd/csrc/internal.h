@@ -72,6 +72,15 @@ void kkt64(hipStream_t s, int problem, int m, int nd, int split, const float* A,
            const float* b, int ldb, const float* x, int ldx, const float* e, int lde,
            const float* y, int ldy, const float* eps, double lambda, int N, double* rbuf,
            double* report);
+// The same report with its two products over the whole batch on the FP64
+// matrix cores: R = b - A x (- e) and G = A^T u (u = y, or R / lambda for
+// QP_lambda).  A64 is the dictionary (m x nd, ld m) in FP64; R (m x N),
+// X (nd x N), U (m x N) and G (nd x N) are workspaces.
+void kkt64_batched(hipStream_t s, int problem, int m, int nd, int split, const double* A64,
+                   const float* b, int ldb, const float* x, int ldx, const float* e, int lde,
+                   const float* y, int ldy, const float* eps, double lambda, int N, double* R,
+                   double* X, double* U, double* G, double* report);
+void to_f64(hipStream_t s, long n, const float* src, double* dst);
 
 // ---- iteration kernels ---------------------------------------------------
 // Arithmetic of a product.  Phase p of an instance selects PHASE_PREC[p].

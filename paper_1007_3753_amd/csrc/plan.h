@@ -71,6 +71,12 @@ struct Plan {
   int* ints = nullptr;    // lists and counters
   long long* stat = nullptr;
   double* kkt_rbuf = nullptr;
+  // the batched FP64 report's dictionary and workspaces (allocated by its
+  // first call, held with the plan)
+  double* kkt_A64 = nullptr;
+  double* kkt_X = nullptr;
+  double* kkt_U = nullptr;
+  double* kkt_G = nullptr;
   int* h_total = nullptr; // pinned
   // the tail kernel's uncached exchange region (barrier, flags, u and
   // partial sums), owned by this plan and given back to the device's free
