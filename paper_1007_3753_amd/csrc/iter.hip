@@ -273,8 +273,13 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
   // XCD-aware tile order: consecutive workgroups are dispatched round-robin
   // to the 8 XCDs, so workgroup L runs on XCD L % 8.  Each XCD takes a
   // contiguous band of row tiles, keeping its slice of the operator in its
-  // own L2 across column tiles; the workgroups of one XCD that share a
-  // column tile run side by side and share the B tile in L2.
+  // own L2 across column tiles.  Within the band the XCD's workgroups go
+  // through groups of TGR row tiles, all column tiles of a group before the
+  // next, rows fastest: the workgroups resident at once then cover about as
+  // many row tiles as column tiles (8 x 8 at two per CU), so each operator
+  // tile and each B tile fetched into L2 serves about 8 workgroups side by
+  // side in K (with the band's rows fastest across all column tiles, a
+  // 4800 x 2100 band of 13-14 row tiles met only 4-5 column tiles at a time).
   const int L = blockIdx.x, xcd = L & 7, j = L >> 3;
   const int RT = a.M / 64;
   // row tiles of partial sums the test adds (all of the iteration's, also
@@ -283,9 +288,12 @@ __global__ __launch_bounds__(256, FAM == 1 ? 2 : 1) void gemm_kernel(GemmArgs a)
   const int r_lo = (xcd * RT) / 8, r_hi = ((xcd + 1) * RT) / 8, nr = r_hi - r_lo;
   if (nr <= 0) return;
   const int ks = (EPI == EPI_PARTIAL) ? a.ksplit : 1;
-  const int rt = r_lo + j % nr, rest = j / nr;
-  const int ct = rest % a.n_ctiles, split = rest / a.n_ctiles;
+  constexpr int TGR = 8;
+  const int per = nr * a.n_ctiles, split = j / per, jj = j - split * per;
   if (split >= ks) return;
+  const int gi = jj / (TGR * a.n_ctiles), gr = min(TGR, nr - gi * TGR);
+  const int loc = jj - gi * TGR * a.n_ctiles;
+  const int rt = r_lo + gi * TGR + loc % gr, ct = loc / gr;
   const int i0 = rt * 64, slot0 = ct * 64;
   int nslots, prec;
   if (a.slot_col) {
