@@ -217,7 +217,12 @@ int l1_alm_backward(l1_alm_plan_t plan, const float* gx_dev, const float* ge_dev
  * report_dev[4*j + {0,1,2,3}] = {relative primal residual, dual infeasibility
  * max(||A^T y||_inf - 1, 0), sign disagreement on the support, relative
  * gap} for instance j.  Arguments as in l1_alm_solve; e_dev / y_dev may be
- * NULL when the problem has no such block (y is not used for QP_lambda). */
+ * NULL when the problem has no such block (y is not used for QP_lambda).
+ * The residual b - A x (- e) and A^T u are formed as FP64 matrix-core GEMMs
+ * over the batch; the first call on a plan allocates their operands (the
+ * dictionary in FP64 and workspaces, 8 (m n_dict + (2 n_dict + m) max_batch)
+ * bytes), held until l1_alm_destroy.  l1_alm_kkt_noalloc computes the same
+ * report without a plan or any allocation.                               */
 int l1_alm_kkt(l1_alm_plan_t plan, const float* b_dev, int ldb, int N,
                const float* eps_dev, const float* x_dev, int ldx,
                const float* e_dev, int lde, const float* y_dev, int ldy,
