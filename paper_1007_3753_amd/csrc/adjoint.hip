@@ -132,6 +132,33 @@ __global__ void scale_cols64_kernel(int rows, int N, const float* src, int lds, 
 }
 
 // out(i, c) = src(i, c) * scale[c] (FP64 -> FP32), overwrite
+// dst (rows_pad x ldd, row-major) = src^T for src (rows x cols, column-major,
+// ld lds), zero in the padding: the K-contiguous operand layout of the
+// iteration GEMM.  32 x 32 tiles through LDS, both sides coalesced.
+__global__ __launch_bounds__(256) void transpose_pad_kernel(int rows, int cols, const float* src,
+                                                            int lds, float* dst, int ldd) {
+  __shared__ float t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    t[k][tx] = (c < cols && r < rows) ? src[(long)c * lds + r] : 0.0f;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (c < ldd) dst[(long)r * ldd + c] = t[tx][k];
+  }
+}
+// D (FP64, n x n, ld ldd) += S (FP32, n x n, ld lds)
+__global__ void add_f32_to_f64_kernel(int n, const float* S, int lds, double* D, int ldd) {
+  const long total = (long)n * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    D[i + (long)j * ldd] += (double)S[i + (long)j * lds];
+  }
+}
+
 __global__ void store_cols_kernel(int rows, int N, const double* src, int lds, const float* scale,
                                   float* out, int ldo) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,8 +224,12 @@ void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* 
   float* seg_u = bf.get<float>(st * every);
   double* cbar = bf.get<double>((size_t)n * N);
   double* Pbar = bf.get<double>((size_t)n * n);
-  double* T64a = bf.get<double>((size_t)n * N * every);
-  double* T64b = bf.get<double>((size_t)n * N * every);
+  // the segment's operands of P-bar, K-contiguous FP32 (K = len N padded to
+  // 64), and its FP32 product
+  const int cpad = (N * every + 63) / 64 * 64;
+  float* VtT = bf.get<float>((size_t)n_pad * cpad);
+  float* UT = bf.get<float>((size_t)n_pad * cpad);
+  float* Pseg = bf.get<float>((size_t)n_pad * n);
   L1_HIP(hipMemsetAsync(Vt, 0, sizeof(float) * st, s));
   L1_HIP(hipMemsetAsync(Ub, 0, sizeof(float) * st, s));
   L1_HIP(hipMemsetAsync(cbar, 0, sizeof(double) * n * N, s));
@@ -300,14 +331,32 @@ void backward_dalm(Plan* p, const float* gx, const float* ge, float* gb, float* 
           cbar);
       L1_HIP(hipGetLastError());
     }
-    // Pbar += [vt_k0 .. vt_{k1-1}] [u_k0 .. u_{k1-1}]^T (FP64)
-    const int cols = len * N;
-    scale_cols64_kernel<<<blocks_for((long)n * cols), 256, 0, s>>>(n, cols, seg_vt, lds, nullptr,
-                                                                   T64a, n);
-    scale_cols64_kernel<<<blocks_for((long)n * cols), 256, 0, s>>>(n, cols, seg_u, lds, nullptr,
-                                                                   T64b, n);
+    // Pbar += [vt_k0 .. vt_{k1-1}] [u_k0 .. u_{k1-1}]^T: the segment's sum
+    // of len N outer products on the FP32 matrix cores (relative rounding
+    // ~1e-7 sqrt(len N), well inside the gradient's 1e-3), accumulated over
+    // the segments in FP64, where the assembly below cancels its terms
+    const int cols = len * N, kp = (cols + 63) / 64 * 64;
+    const dim3 tg((unsigned)(kp / 32), (unsigned)(n_pad / 32));
+    transpose_pad_kernel<<<tg, 256, 0, s>>>(n, cols, seg_vt, lds, VtT, kp);
+    transpose_pad_kernel<<<tg, 256, 0, s>>>(n, cols, seg_u, lds, UT, kp);
     L1_HIP(hipGetLastError());
-    gemm64(s, 'N', 'T', n, n, cols, 1.0, T64a, n, T64b, n, 1.0, Pbar, n);
+    {
+      GemmArgs pg{};
+      pg.A32 = VtT;
+      pg.lda = kp;
+      pg.B = UT;
+      pg.ldb = kp;
+      pg.M = n_pad;
+      pg.K = kp;
+      pg.n_cols = n;
+      pg.prec = PREC_F32;
+      pg.m_true = n;
+      pg.out = Pseg;
+      pg.ldo = n_pad;
+      launch_gemm(s, EPI_STORE, pg, (n + TILE - 1) / TILE);
+    }
+    add_f32_to_f64_kernel<<<blocks_for((long)n * n), 256, 0, s>>>(n, Pseg, n_pad, Pbar, n);
+    L1_HIP(hipGetLastError());
   }
 
   // ---- FP64 assembly -------------------------------------------------------
